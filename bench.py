@@ -1,0 +1,197 @@
+"""Throughput of the coupled D3Q19 / D3Q7 phase-change step on one MI355X.
+
+Headline workload: natural-convection melting in a 128^3 cavity (Ra = 1e5,
+Pr = 0.02, Ste = 0.1), D3Q19 MRT flow + D3Q7 MRT enthalpy, FP32 storage and
+arithmetic, synthetic initial state (solid at T_m, hot wall at T_h = 1).
+One step = the whole fused step for every cell (collisions, buoyancy and
+solid-region forcing, streaming with walls, enthalpy -> (T, f_l)) plus its
+FP64 budget partials; reductions of the partials run inside the timed region.
+
+Prints one JSON line.  value = MLUPS (million cell updates per second).
+Extra figures (256^3 16-bit storage, the 64-cavity batch, the adjoint/forward
+cost ratio at 96^3) go into "extras".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {0: 416, 1: 208, 2: 108, 3: 108}   # populations read + written once
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(cav, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_cavity(cfg, steps, warmup, launch=None, label=""):
+    from paper_1703_02652_amd import Cavity
+    cav = Cavity(cfg, device="cuda")
+    best = None
+    if launch:
+        cav.set_launch(*launch)
+    else:
+        best = cav.autotune(10)
+    cav.step(warmup)
+    dt = timed_steps(cav, steps)
+    kern_ms = cav.time_step_kernel(20)
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    mlups = cells * steps / dt / 1e6
+    log(f"[bench] {label}: {mlups:.0f} MLUPS, {1e3 * dt / steps:.4f} ms/step, kernel "
+        f"{kern_ms:.4f} ms, launch {cav.get_launch()} (tuned {best})")
+    st = cav.status()
+    return cav, dict(mlups=mlups, ms_per_step=1e3 * dt / steps, kernel_ms=kern_ms,
+                     launch=list(cav.get_launch()), unstable=int(st.max()))
+
+
+def cpu_baseline(cfg, target_s=10.0, max_steps=40):
+    """The FP64 CPU oracle on the same workload, a bounded number of steps."""
+    import oracle
+    st = oracle.init_state(cfg)
+    t = time.perf_counter()
+    st = oracle.run(cfg, st, 1)
+    t1 = time.perf_counter() - t
+    n = int(max(1, min(max_steps, target_s / max(t1, 1e-3))))
+    t = time.perf_counter()
+    oracle.run(cfg, st, n)
+    dt = time.perf_counter() - t
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    return dict(value=cells * n / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
+                sample=f"{cfg['nx']}x{cfg['ny']}x{cfg['nz']} coupled FP64 oracle, {n} steps "
+                       f"from the same initial state ({dt:.1f} s)")
+
+
+def adjoint_ratio(prec, n=96, steps=200, every=100):
+    import torch
+    import workloads as W
+    from paper_1703_02652_amd import Cavity
+    cfg = W.adjoint_cavity(n, precision=prec)
+    cav = Cavity(cfg, device="cuda")
+    cav.set_wall_T(0, W.hot_wall_field(n, n))
+    cav.autotune(5)
+    state = cav.save()
+    t_fwd = timed_steps(cav, steps)
+    cav.load(state)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cav.adjoint_forward(steps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cav.adjoint_backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return dict(precision=["fp64", "fp32"][prec], cells=n**3, steps=steps, ckpt_every=every,
+                forward_ms_per_step=1e3 * t_fwd / steps,
+                backward_ms_per_step=1e3 * (t2 - t1) / steps,
+                backward_over_forward=(t2 - t1) / t_fwd,
+                total_over_forward=(t2 - t0) / t_fwd)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="block,grid,graph_steps instead of autotuning")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 10 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calibrate_copy_bytes=a.numel() * 4, dispatches=10)))
+        return
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+
+    cfg = W.cavity_128(precision=W.FP32)
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    cav, main_r = run_cavity(cfg, args.steps, args.warmup, launch=launch, label="cavity128 fp32")
+    alg_bytes = BYTES_PER_CELL[W.FP32] * cells
+    achieved = alg_bytes / (main_r["kernel_ms"] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel="k_step<fp32, flow, MRT, budgets>",
+                    bytes_per_launch=alg_bytes, kernel_ms=round(main_r["kernel_ms"], 5))
+    cav.close()
+    del cav
+
+    extras = {}
+    if not args.no_extras:
+        xs = max(50, args.steps // 5)
+        for name, prec in (("cavity256_fp32", W.FP32), ("cavity256_fp16s", W.FP16S),
+                           ("cavity256_bf16s", W.BF16S)):
+            c = W.precision_cavity(256, 0.02, precision=prec)
+            cv, r = run_cavity(c, xs, 20, label=name)
+            r["hbm_frac"] = round(BYTES_PER_CELL[prec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
+                                  / HBM_PEAK_GBS, 4)
+            extras[name] = r
+            cv.close()
+            del cv
+            torch.cuda.empty_cache()
+        from paper_1703_02652_amd import Cavity
+        bcfgs, _ = W.batch_cavities()
+        bc = Cavity(bcfgs, device="cuda")
+        bc.autotune(5)
+        bc.step(20)
+        dt = timed_steps(bc, xs)
+        bcells = sum(c["nx"] * c["ny"] * c["nz"] for c in bcfgs)
+        extras["batch64_fp32"] = dict(cells=bcells, mlups=bcells * xs / dt / 1e6,
+                                      ms_per_step=1e3 * dt / xs, launch=list(bc.get_launch()),
+                                      unstable_cavities=int(bc.status().sum()))
+        log(f"[bench] batch64: {extras['batch64_fp32']}")
+        bc.close()
+        del bc
+        torch.cuda.empty_cache()
+        extras["adjoint96_fp32"] = adjoint_ratio(W.FP32)
+        log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
+        extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)
+        log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(W.cavity_128(precision=W.FP64))
+        log(f"[bench] cpu baseline: {cpu}")
+
+    out = dict(
+        metric="coupled flow+enthalpy MLUPS (128^3 cavity, FP32)",
+        value=round(main_r["mlups"], 1), unit="MLUPS", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(main_r["ms_per_step"], 5), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="cavity128_Ra1e5_Pr0.02_Ste0.1", lattice="D3Q19 MRT + D3Q7 MRT",
+                    cells=cells, storage="fp32", launch=main_r["launch"]),
+        roofline=roofline, cpu_baseline=cpu, extras=extras,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

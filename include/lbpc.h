@@ -1,0 +1,191 @@
+/*
+ * lbpc: coupled enthalpy / flow lattice Boltzmann step for solid-liquid phase
+ * change on one MI355X (gfx950).
+ *
+ * Method: Li & He, "Three-dimensional lattice Boltzmann models for solid-liquid
+ * phase change" (arXiv 1703.02652).  One time step does, for every cell:
+ *   - h = sum_a g_a and the enthalpy -> (T, f_l) rule, Eq. (2) (Sec. 2.1);
+ *   - D3Q7 enthalpy collision, SRT Eq. (5)-(8) or MRT Eq. (21)-(25) with the
+ *     relaxation rule of Eq. (47) (Sec. 2.2-2.4);
+ *   - D3Q19 MRT flow collision with Boussinesq buoyancy, Eq. (48)-(56)
+ *     (Sec. 2.5), restricted to the liquid by a solid-region forcing that makes
+ *     u = f_l (sum f e + F_b / 2) / rho;
+ *   - streaming of both distributions with halfway bounce-back walls, fixed-
+ *     temperature (anti-bounce-back) and adiabatic thermal walls (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - Lattice units: delta_x = delta_t = c = 1.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary host memory.  The library never allocates device
+ *     memory: the caller provides the workspace and every output buffer.
+ *   - Cell order is x fastest: cell = x + nx * (y + ny * z).  Population
+ *     arrays are planes [q][cell].
+ *   - Work is enqueued on the HIP stream given at creation, in order.  Calls
+ *     that return host data synchronise that stream.
+ *   - Return codes: LBPC_OK (0) or a negative LBPC_E* code; the context keeps
+ *     a message for lbpc_last_error().  No C++ exception crosses this ABI.
+ *   - A context is not thread-safe; calls on one context must be serialised.
+ */
+#ifndef LBPC_H_
+#define LBPC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBPC_OK = 0,
+  LBPC_EINVAL = -1,     /* bad argument or configuration */
+  LBPC_EHIP = -2,       /* a HIP runtime call failed */
+  LBPC_ENOSPACE = -3,   /* workspace smaller than required */
+  LBPC_EUNSTABLE = -4   /* a cavity produced a non-finite or out-of-bound state */
+};
+
+/* Face order everywhere: x-, x+, y-, y+, z-, z+ (walls half a cell outside the
+ * first and last nodes). */
+enum {
+  LBPC_PERIODIC = 0,    /* both faces of the pair must be periodic */
+  LBPC_DIRICHLET = 1,   /* fixed temperature (anti-bounce-back) + no-slip */
+  LBPC_ADIABATIC = 2    /* zero heat flux (bounce-back) + no-slip */
+};
+
+/* Population storage.  The shifted formats store f_a - w_a rho0 (the deviation
+ * from rest); g_0 is kept in FP32 in the 16-bit formats; collision arithmetic
+ * is FP32 for every format but FP64. */
+enum { LBPC_FP64 = 0, LBPC_FP32 = 1, LBPC_FP16S = 2, LBPC_BF16S = 3 };
+enum { LBPC_SRT = 0, LBPC_MRT = 1 };
+
+/* Field mask bits for lbpc_fields; planes are written in this bit order. */
+enum {
+  LBPC_FIELD_H = 1, LBPC_FIELD_T = 2, LBPC_FIELD_FL = 4, LBPC_FIELD_RHO = 8,
+  LBPC_FIELD_U = 16 /* three planes: u_x, u_y, u_z */
+};
+
+/* One cavity (plain data, lattice units).
+ * thermal: omega_T fixes the D3Q7 weights w_0 = 1 - 3 omega_T, w_a = omega_T / 2
+ *   (Eq. (8)); the conductivity lambda gives chi = lambda / (rho0 cp_ref) and
+ *   tau_g = chi / omega_T + 1/2, sigma_chi = 1 / tau_g (Eq. (20), (34)); local
+ *   lambda and C_p are linear in f_l between the solid and liquid values.
+ *   Default MRT rates: sigma_0..3 = sigma_chi, sigma_4..6 = 2 - sigma_chi
+ *   (Eq. (47)); a finite sigma_override[k] replaces rate k (NaN keeps it).
+ * flow: nu gives s_nu = 1 / (3 nu + 1/2) (Eq. (59)); s_e, s_eps, s_q, s_pi, s_t
+ *   are the remaining diagonal entries of Eq. (52); the buoyancy is
+ *   F_z = rho0 g_beta (T - T_ref) (Eq. (55)).  flow = 0 runs the enthalpy
+ *   distribution alone with u = 0. */
+typedef struct lbpc_config {
+  int32_t nx, ny, nz;
+  int32_t flow;         /* 0: enthalpy only, 1: coupled D3Q19 flow */
+  int32_t enth_model;   /* LBPC_SRT or LBPC_MRT */
+  int32_t precision;    /* LBPC_FP64 ... LBPC_BF16S; same for every cavity of a batch */
+  int32_t face_bc[6];
+  double face_T[6];     /* wall temperature of LBPC_DIRICHLET faces */
+  double omega_T, cp_s, cp_l, cp_ref, lambda_s, lambda_l, latent, T_m, rho0;
+  double nu, s_e, s_eps, s_q, s_pi, s_t, g_beta, T_ref;
+  double sigma_override[7];
+} lbpc_config;
+
+typedef struct lbpc_ctx lbpc_ctx;
+
+/* Device bytes the caller must provide to lbpc_create for this batch (state
+ * double buffer, parameter and tile tables, wall fields, budget partials).
+ * Returns 0 for an invalid configuration. */
+size_t lbpc_workspace_bytes(const lbpc_config* cfgs, int32_t batch);
+
+/* Validate cfgs[0..batch), lay out the caller-owned workspace and initialise
+ * every cavity at rest: f = w rho0 and g = g^eq(h0(T0), T0, u = 0) (Eq. (7)),
+ * with h0 = C_p,s T0 for T0 <= T_m and C_p,l T0 + L above (Eq. (2)).
+ * dev_T0: nullable FP64 device array of all cavities' cells back to back
+ * (NULL: T0 = T_m everywhere).  hip_stream: hipStream_t (NULL = default).
+ * The workspace must stay allocated until lbpc_destroy. */
+int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, size_t bytes,
+                const double* dev_T0, void* hip_stream, lbpc_ctx** out);
+
+/* Replace the temperature of one fixed-temperature face by a per-node field
+ * (FP64 device array, copied).  Node layout: x faces [nz][ny], y faces
+ * [nz][nx], z faces [ny][nx]. */
+int lbpc_set_wall_T(lbpc_ctx* ctx, int32_t cavity, int32_t face, const double* dev_Tw);
+
+/* Advance every cavity by nsteps time steps (asynchronous).  Returns
+ * LBPC_EUNSTABLE, without stepping, once a cavity has been flagged. */
+int lbpc_step(lbpc_ctx* ctx, int64_t nsteps);
+
+/* Macroscopic fields of the current (pre-collision) state of one cavity, FP64
+ * planes of nx*ny*nz values in mask-bit order; u is the forced velocity
+ * u = f_l (sum f e + F_b / 2) / rho (zero without flow). */
+int lbpc_fields(lbpc_ctx* ctx, int32_t cavity, uint32_t mask, double* dev_out);
+
+/* Per cavity, 5 FP64 values: H = sum h, mass = sum rho, sum f_l (current
+ * state), the enthalpy that entered through fixed-temperature walls since
+ * creation, and the number of steps taken.  Deterministic summation order.
+ * Synchronises the stream. */
+int lbpc_budgets(lbpc_ctx* ctx, double* host_out);
+
+/* Per-cavity status bits (1 = non-finite or out-of-bound state seen; such a
+ * cavity is frozen).  Synchronises the stream. */
+int lbpc_status(lbpc_ctx* ctx, int32_t* host_flags);
+
+/* Pre-collision populations of one cavity decoded to FP64: dev_f 19 planes
+ * (ignored without flow, may be NULL), dev_g 7 planes.  Velocity order of
+ * Eq. (48) and Eq. (3). */
+int lbpc_get_state(lbpc_ctx* ctx, int32_t cavity, double* dev_f, double* dev_g);
+/* Overwrite the state of one cavity from FP64 planes (encoded to the storage
+ * format; dev_f ignored without flow). */
+int lbpc_set_state(lbpc_ctx* ctx, int32_t cavity, const double* dev_f, const double* dev_g);
+
+/* Raw checkpoint of the whole batch (populations in storage format, budgets
+ * and step counter).  lbpc_load of a buffer from lbpc_save restores the run
+ * bit for bit.  Synchronise the stream. */
+size_t lbpc_state_bytes(const lbpc_ctx* ctx);
+int lbpc_save(lbpc_ctx* ctx, void* host_buf, size_t bytes);
+int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Launch configuration.  block: threads (and cells) per tile, 64..256, a
+ * multiple of 64; grid_blocks: 0 for one workgroup per tile, else a persistent
+ * grid that strides over the tile queue; graph_steps: steps per captured HIP
+ * graph (even, 0 disables graphs). */
+int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t graph_steps);
+int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
+                    int32_t* graph_steps);
+
+/* Time every candidate launch configuration on the real state (the state is
+ * not advanced) and keep the fastest.  host_ms_out (nullable) receives the
+ * best average step-kernel time in milliseconds.  Synchronises the stream. */
+int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
+
+/* Advance nsteps with a HIP event pair around each step-kernel launch; the
+ * mean kernel time in milliseconds goes to host_ms_out.  Synchronises. */
+int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
+
+/* Discrete adjoint of the loss L = sum over cells of f_l at the final step
+ * (loss = 0) or L / (ny nz), the interface position of a front along x
+ * (loss = 1), w.r.t. the wall temperatures and the initial temperature field.
+ * Single-cavity contexts in LBPC_FP64 or LBPC_FP32 only.
+ *   lbpc_adjoint_workspace_bytes: device bytes for nsteps with a checkpoint every
+ *     ckpt_every steps (snapshots, one segment of recomputed states, adjoint
+ *     populations).
+ *   lbpc_adjoint_forward: run nsteps from the current state, storing
+ *     checkpoints in dev_adj_ws; the state is left at the final step; the loss
+ *     goes to host_loss (synchronises).
+ *   lbpc_adjoint_backward: reverse sweep with recomputation per segment; seed
+ *     scales the loss (dL/dL = seed).  dev_dL_dTw: FP64, all six faces'
+ *     node fields back to back (layout of lbpc_set_wall_T), zero on faces
+ *     that are not fixed-temperature.  dev_dL_dT0: FP64 per cell, the
+ *     derivative w.r.t. the initial temperature of lbpc_create (one-sided,
+ *     solid side, at T0 = T_m); only valid when the forward started from the
+ *     state made by lbpc_create.  Either output may be NULL. */
+size_t lbpc_adjoint_workspace_bytes(const lbpc_ctx* ctx, int64_t nsteps, int32_t ckpt_every);
+int lbpc_adjoint_forward(lbpc_ctx* ctx, int64_t nsteps, int32_t ckpt_every, int32_t loss,
+                         void* dev_adj_ws, size_t bytes, double* host_loss);
+int lbpc_adjoint_backward(lbpc_ctx* ctx, double seed, double* dev_dL_dTw, double* dev_dL_dT0);
+
+void lbpc_destroy(lbpc_ctx* ctx);
+const char* lbpc_last_error(const lbpc_ctx* ctx);
+const char* lbpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBPC_H_ */

@@ -1,0 +1,103 @@
+// Internal interface between the runtime (lbpc_runtime.hip) and the kernel
+// translation units (one per storage format).  Plain data only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbpc {
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
+enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_ADIABATIC = 2 };
+
+// Per-cavity constants, read by every workgroup of that cavity through scalar
+// loads (the cavity index of a tile is uniform across the workgroup).
+struct alignas(16) CavParams {
+  int32_t nx, ny, nz, n;        // n = nx * ny * nz (< 2^31)
+  int32_t nxy;
+  int32_t bc[6];
+  int32_t tile0, ntiles;        // this cavity's tiles in the tile queue
+  int32_t has_override;         // any finite sigma_override entry
+  uint64_t div_nx_m, div_nxy_m; // magic multipliers: q = (i * m) >> s
+  uint32_t div_nx_s, div_nxy_s;
+  int64_t off;                  // byte offset of the cavity inside a state region
+  int64_t plane;                // elements between population planes
+  int64_t cell_off;             // first cell of the cavity in batch-wide cell arrays
+  const double* tw;             // this cavity's wall-temperature fields (6 faces)
+  int64_t twface[6];            // offset of each face inside tw
+  // thermal
+  double omega_T, cp_s, cp_l, cp_ref, lam_s, lam_l, latent, T_m, rho0;
+  double hs, hl, inv_dh, inv_cps, inv_cpl, inv_rcw;  // inv_rcw = 1/(rho0 cp_ref omega_T)
+  double sig_ovr[7];            // NaN: default rate
+  // flow
+  double s_nu, s_e, s_eps, s_q, s_pi, s_t, g_beta_rho0, T_ref;
+  double fshift;                // rho0 for shifted storage, 0 for raw FP64
+};
+
+// Device-side budget record of one cavity.
+struct alignas(16) BudgetRec {
+  double H, mass, fl;           // pre-collision sums of the last reduced step
+  double flux_last, flux_cum;   // wall enthalpy inflow: last step, since creation
+  double steps;                 // steps reduced so far
+  double now_H, now_mass, now_fl;  // sums of the current state (measure pass)
+  double pad[3];
+};
+
+constexpr int NPART = 5;        // per-tile partials: h, rho, f_l, wall flux, bad cells
+
+struct StepArgs {
+  const CavParams* cavs;
+  const int2* tiles;            // (cavity, first cell) per tile
+  int ntiles;
+  const char* src;              // state region read (pre-collision state at t)
+  char* dst;                    // state region written (pre-collision state at t+1)
+  double* partials;             // NPART doubles per tile, or null (no budgets)
+  const int32_t* status;        // per-cavity freeze flags
+  int block, grid;              // grid = 0: one workgroup per tile
+  int flow, mrt;
+  hipStream_t stream;
+};
+
+struct AdjArgs {
+  const CavParams* cavs;
+  const int2* tiles;
+  int ntiles;
+  const char* state;            // state at t (storage format)
+  const char* lam_in;           // adjoint of the state at t+1 (compute format)
+  char* lam_out;                // adjoint of the state at t
+  double* dTw;                  // wall-temperature gradient accumulators (per cavity block)
+  int block;
+  int flow, mrt;
+  hipStream_t stream;
+};
+
+template <int P> hipError_t launch_step(const StepArgs& a);
+template <int P> hipError_t launch_init(const CavParams* cavs, const int2* tiles, int ntiles,
+                                        int block, int flow, char* dst, const double* T0,
+                                        hipStream_t st);
+template <int P> hipError_t launch_measure(const CavParams* cavs, const int2* tiles, int ntiles,
+                                           int block, int flow, const char* src,
+                                           double* partials, hipStream_t st);
+// single-cavity launchers: cav is a device pointer into the parameter table
+template <int P> hipError_t launch_fields(const CavParams* cav, int64_t n, int flow,
+                                          const char* src, uint32_t mask, double* out,
+                                          hipStream_t st);
+template <int P> hipError_t launch_get_state(const CavParams* cav, int64_t n, int flow,
+                                             const char* src, double* f, double* g,
+                                             hipStream_t st);
+template <int P> hipError_t launch_set_state(const CavParams* cav, int64_t n, int flow,
+                                             char* dst, const double* f, const double* g,
+                                             hipStream_t st);
+template <int P> hipError_t launch_adjoint(const AdjArgs& a);
+template <int P> hipError_t launch_adj_seed(const CavParams* cav, int64_t n, int flow,
+                                            double scale, const char* state, char* lam,
+                                            hipStream_t st);
+template <int P> hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int flow,
+                                          const char* state0, const char* lam, double* out,
+                                          hipStream_t st);
+
+hipError_t launch_reduce(const CavParams* cavs, int batch, const double* partials,
+                         int64_t slot_stride, int nslots, int mode, BudgetRec* rec,
+                         int32_t* status, hipStream_t st);
+hipError_t launch_fill(void* p, int64_t nbytes, hipStream_t st);
+
+}  // namespace lbpc

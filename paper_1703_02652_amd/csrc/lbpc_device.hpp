@@ -1,0 +1,642 @@
+// Device code of the coupled D3Q19 / D3Q7 phase-change lattice Boltzmann step
+// (Li & He, arXiv 1703.02652) for gfx950.  Included by the per-format kernel
+// translation units only.
+//
+// Layout: every cavity owns, inside a state region, 19 f planes, 6 planes for
+// g_1..g_6 and one plane for g_0, each plane `plane` elements long, cell index
+// x + nx (y + ny z).  FP64 stores the populations as they are; the other
+// formats store f_a - w_a rho0 (deviation from rest), g_0 in FP32.
+//
+// Step scheme: one thread per cell reads its own pre-collision populations
+// (aligned, coalesced), does both collisions in registers and pushes every
+// post-collision population to the cell it streams to (a bijection, so no
+// write conflicts).  The stored state is therefore always the pre-collision
+// state of Eq. (5) / Eq. (50), the one the fields and the adjoint are defined on.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbpc_api.hpp"
+
+namespace lbpc {
+
+// ---------------------------------------------------------------------------
+// Storage formats
+// ---------------------------------------------------------------------------
+struct bf16 {
+  uint16_t b;
+};
+
+template <int P> struct Fmt;
+template <> struct Fmt<P64> { using S = double;   using S0 = double; using R = double; };
+template <> struct Fmt<P32> { using S = float;    using S0 = float;  using R = float; };
+template <> struct Fmt<P16> { using S = _Float16; using S0 = float;  using R = float; };
+template <> struct Fmt<PB16> { using S = bf16;    using S0 = float;  using R = float; };
+
+__device__ __forceinline__ double dec(double v) { return v; }
+__device__ __forceinline__ float dec(float v) { return v; }
+__device__ __forceinline__ float dec(_Float16 v) { return static_cast<float>(v); }
+__device__ __forceinline__ float dec(bf16 v) { return __uint_as_float(static_cast<uint32_t>(v.b) << 16); }
+
+template <class S> __device__ __forceinline__ S enc(double v);
+template <> __device__ __forceinline__ double enc<double>(double v) { return v; }
+template <> __device__ __forceinline__ float enc<float>(double v) { return static_cast<float>(v); }
+template <> __device__ __forceinline__ _Float16 enc<_Float16>(double v) {
+  return static_cast<_Float16>(static_cast<float>(v));
+}
+template <> __device__ __forceinline__ bf16 enc<bf16>(double v) {
+  // round to nearest even on the upper 16 bits of the FP32 pattern
+  uint32_t u = __float_as_uint(static_cast<float>(v));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{static_cast<uint16_t>(u >> 16)};
+}
+
+template <int P> struct View {
+  using S = typename Fmt<P>::S;
+  using S0 = typename Fmt<P>::S0;
+  S* f;     // 19 planes (only with flow)
+  S* g;     // g_1..g_6 planes
+  S0* g0;   // g_0 plane
+  int64_t plane;
+};
+
+template <int P>
+__device__ __forceinline__ View<P> view(const char* region, const CavParams& c, bool flow) {
+  using S = typename Fmt<P>::S;
+  using S0 = typename Fmt<P>::S0;
+  View<P> v;
+  v.plane = c.plane;
+  v.f = reinterpret_cast<S*>(const_cast<char*>(region) + c.off);
+  v.g = v.f + (flow ? 19 * c.plane : 0);
+  v.g0 = reinterpret_cast<S0*>(v.g + 6 * c.plane);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Lattices (velocity order of Eq. (48) for D3Q19 and Eq. (3) for D3Q7)
+// ---------------------------------------------------------------------------
+constexpr int Q19X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int Q19Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int Q19Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int Q19OPP[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+constexpr int Q7X[7] = {0, 1, -1, 0, 0, 0, 0};
+constexpr int Q7Y[7] = {0, 0, 0, 1, -1, 0, 0};
+constexpr int Q7Z[7] = {0, 0, 0, 0, 0, 1, -1};
+constexpr int Q7OPP[7] = {0, 2, 1, 4, 3, 6, 5};
+// D3Q19 rest weights (equilibrium at u = 0: 1/3, 1/18, 1/36)
+constexpr double W19[19] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                            1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+__device__ __forceinline__ uint32_t fastdiv(uint32_t i, uint64_t m, uint32_t s) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(i) * m) >> s);
+}
+
+struct Site {
+  int32_t x, y, z, cell;
+  bool lx, hx, ly, hy, lz, hz;
+};
+
+__device__ __forceinline__ Site make_site(const CavParams& c, int32_t cell) {
+  Site s;
+  s.cell = cell;
+  s.z = static_cast<int32_t>(fastdiv(static_cast<uint32_t>(cell), c.div_nxy_m, c.div_nxy_s));
+  const int32_t r = cell - s.z * c.nxy;
+  s.y = static_cast<int32_t>(fastdiv(static_cast<uint32_t>(r), c.div_nx_m, c.div_nx_s));
+  s.x = r - s.y * c.nx;
+  s.lx = s.x == 0;
+  s.hx = s.x == c.nx - 1;
+  s.ly = s.y == 0;
+  s.hy = s.y == c.ny - 1;
+  s.lz = s.z == 0;
+  s.hz = s.z == c.nz - 1;
+  return s;
+}
+
+// Cell reached by moving one link (ex, ey, ez) from s; periodic faces wrap.
+// face >= 0 when the link leaves through a non-periodic face (the last such
+// face for a diagonal that crosses two).
+__device__ __forceinline__ int32_t link_target(const CavParams& c, const Site& s, int ex, int ey,
+                                               int ez, int& face) {
+  int32_t idx = s.cell + ex + ey * c.nx + ez * c.nxy;
+  face = -1;
+  if (ex > 0 && s.hx) { if (c.bc[1] == BC_PERIODIC) idx -= c.nx; else face = 1; }
+  if (ex < 0 && s.lx) { if (c.bc[0] == BC_PERIODIC) idx += c.nx; else face = 0; }
+  if (ey > 0 && s.hy) { if (c.bc[3] == BC_PERIODIC) idx -= c.nxy; else face = 3; }
+  if (ey < 0 && s.ly) { if (c.bc[2] == BC_PERIODIC) idx += c.nxy; else face = 2; }
+  if (ez > 0 && s.hz) { if (c.bc[5] == BC_PERIODIC) idx -= c.n; else face = 5; }
+  if (ez < 0 && s.lz) { if (c.bc[4] == BC_PERIODIC) idx += c.n; else face = 4; }
+  return idx;
+}
+
+// Node of a face field seen by the cell at s: x faces [nz][ny], y faces
+// [nz][nx], z faces [ny][nx].
+__device__ __forceinline__ int64_t face_node(const CavParams& c, const Site& s, int face) {
+  const int dim = face >> 1;
+  if (dim == 0) return s.y + static_cast<int64_t>(c.ny) * s.z;
+  if (dim == 1) return s.x + static_cast<int64_t>(c.nx) * s.z;
+  return s.x + static_cast<int64_t>(c.nx) * s.y;
+}
+
+// ---------------------------------------------------------------------------
+// Cell physics
+// ---------------------------------------------------------------------------
+// Enthalpy -> (T, f_l), Eq. (2) with h0 = 0, as the lever rule: solid for
+// h <= h_s = C_p,s T_m, liquid for h >= h_l = C_p,l T_m + L, isothermal at T_m
+// in between.  FP64 for every storage format.
+__device__ __forceinline__ void phase_rule(const CavParams& c, double h, double& T, double& fl) {
+  if (h <= c.hs) {
+    fl = 0.0;
+    T = h * c.inv_cps;
+  } else if (h >= c.hl) {
+    fl = 1.0;
+    T = (h - c.latent) * c.inv_cpl;
+  } else {
+    fl = (h - c.hs) * c.inv_dh;
+    T = c.T_m;
+  }
+}
+
+// Macroscopic flow variables and forces of one cell (Eq. (55), (56)) with the
+// solid-region forcing u = f_l j / rho, j = sum f e + F_b / 2; d holds the
+// stored deviations f - fshift w.
+template <class R> struct FlowMacro {
+  R dr, rho, jx, jy, jz0, ux, uy, uz, Fx, Fy, Fz;
+};
+
+template <class R>
+__device__ __forceinline__ FlowMacro<R> flow_macro(const CavParams& c, const R* d, R T, R fl) {
+  FlowMacro<R> m;
+  R dr = d[0];
+  R jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int a = 1; a < 19; ++a) {
+    dr += d[a];
+    if (Q19X[a] != 0) jx += Q19X[a] > 0 ? d[a] : -d[a];
+    if (Q19Y[a] != 0) jy += Q19Y[a] > 0 ? d[a] : -d[a];
+    if (Q19Z[a] != 0) jz += Q19Z[a] > 0 ? d[a] : -d[a];
+  }
+  m.dr = dr;
+  m.rho = static_cast<R>(c.fshift) + dr;
+  m.jx = jx;
+  m.jy = jy;
+  m.jz0 = jz;
+  const R Fb = static_cast<R>(c.g_beta_rho0) * (T - static_cast<R>(c.T_ref));
+  const R jzb = jz + static_cast<R>(0.5) * Fb;
+  const R irho = static_cast<R>(1) / m.rho;
+  m.ux = fl * jx * irho;
+  m.uy = fl * jy * irho;
+  m.uz = fl * jzb * irho;
+  m.Fx = static_cast<R>(2) * (m.rho * m.ux - jx);
+  m.Fy = static_cast<R>(2) * (m.rho * m.uy - jy);
+  m.Fz = static_cast<R>(2) * (m.rho * m.uz - jz);
+  return m;
+}
+
+// D3Q19 MRT collision with forcing, Eq. (49)-(54), in registers.  The moment
+// basis of Eq. (51) is applied as grouped sums (axis pairs and the three
+// diagonal families); M^-1 = M^T diag(1/|row|^2) because the rows are
+// orthogonal.  Working on deviations d = f - fshift w is exact algebra: the
+// rest state contributes only to the rho, e and epsilon moments.
+template <class R>
+__device__ __forceinline__ void flow_collide(const CavParams& c, R* d, const FlowMacro<R>& q) {
+  const R sx = d[1] + d[2], ax = d[1] - d[2];
+  const R sy = d[3] + d[4], ay = d[3] - d[4];
+  const R sz = d[5] + d[6], az = d[5] - d[6];
+  const R p78 = d[7] + d[8], m78 = d[7] - d[8], p910 = d[9] + d[10], m910 = d[9] - d[10];
+  const R Sxy = p78 + p910, Axy_x = m78 + m910, Axy_y = p78 - p910, Pxy = m78 - m910;
+  const R p1112 = d[11] + d[12], m1112 = d[11] - d[12], p1314 = d[13] + d[14], m1314 = d[13] - d[14];
+  const R Sxz = p1112 + p1314, Axz_x = m1112 + m1314, Axz_z = p1112 - p1314, Pxz = m1112 - m1314;
+  const R p1516 = d[15] + d[16], m1516 = d[15] - d[16], p1718 = d[17] + d[18], m1718 = d[17] - d[18];
+  const R Syz = p1516 + p1718, Ayz_y = m1516 + m1718, Ayz_z = p1516 - p1718, Pyz = m1516 - m1718;
+  const R Sax = sx + sy + sz, Sdg = Sxy + Sxz + Syz;
+
+  const R m1 = static_cast<R>(-30) * d[0] + static_cast<R>(-11) * Sax + static_cast<R>(8) * Sdg;
+  const R m2 = static_cast<R>(12) * d[0] + static_cast<R>(-4) * Sax + Sdg;
+  const R m4 = static_cast<R>(-4) * ax + Axy_x + Axz_x;
+  const R m6 = static_cast<R>(-4) * ay + Axy_y + Ayz_y;
+  const R m8 = static_cast<R>(-4) * az + Axz_z + Ayz_z;
+  const R m9 = static_cast<R>(2) * sx - sy - sz + Sxy + Sxz - static_cast<R>(2) * Syz;
+  const R m10 = static_cast<R>(-4) * sx + static_cast<R>(2) * (sy + sz) + Sxy + Sxz -
+                static_cast<R>(2) * Syz;
+  const R m11 = sy - sz + Sxy - Sxz;
+  const R m12 = static_cast<R>(-2) * (sy - sz) + Sxy - Sxz;
+  const R m16 = Axy_x - Axz_x, m17 = Ayz_y - Axy_y, m18 = Axz_z - Ayz_z;
+
+  const R rho = q.rho, ux = q.ux, uy = q.uy, uz = q.uz, Fx = q.Fx, Fy = q.Fy, Fz = q.Fz;
+  const R u2 = ux * ux + uy * uy + uz * uz;
+  const R Fu = Fx * ux + Fy * uy + Fz * uz;
+  const R s_e = static_cast<R>(c.s_e), s_eps = static_cast<R>(c.s_eps), s_q = static_cast<R>(c.s_q);
+  const R s_nu = static_cast<R>(c.s_nu), s_pi = static_cast<R>(c.s_pi), s_t = static_cast<R>(c.s_t);
+  const R half = static_cast<R>(0.5), one = static_cast<R>(1);
+  const R k_e = one - half * s_e, k_eps = one - half * s_eps, k_q = one - half * s_q;
+  const R k_nu = one - half * s_nu, k_pi = one - half * s_pi;
+  const R two3 = static_cast<R>(2.0 / 3.0);
+  const R p9 = static_cast<R>(3) * ux * ux - u2;
+  const R p11 = uy * uy - uz * uz;
+
+  // Delta_k = Lambda_k (m_k - m_k^eq) - (1 - Lambda_k / 2) FF_k, scaled by 1/|row_k|^2
+  const R a1 = (s_e * (m1 + static_cast<R>(11) * q.dr - static_cast<R>(19) * rho * u2) -
+                k_e * static_cast<R>(38) * Fu) * static_cast<R>(1.0 / 2394.0);
+  const R a2 = (s_eps * (m2 - static_cast<R>(3) * q.dr + static_cast<R>(5.5) * rho * u2) +
+                k_eps * static_cast<R>(11) * Fu) * static_cast<R>(1.0 / 252.0);
+  const R a3 = -Fx * static_cast<R>(0.1);
+  const R a5 = -Fy * static_cast<R>(0.1);
+  const R a7 = -Fz * static_cast<R>(0.1);
+  const R a4 = (s_q * (m4 + two3 * rho * ux) + k_q * two3 * Fx) * static_cast<R>(1.0 / 40.0);
+  const R a6 = (s_q * (m6 + two3 * rho * uy) + k_q * two3 * Fy) * static_cast<R>(1.0 / 40.0);
+  const R a8 = (s_q * (m8 + two3 * rho * uz) + k_q * two3 * Fz) * static_cast<R>(1.0 / 40.0);
+  const R a9 = (s_nu * (m9 - rho * p9) - k_nu * (static_cast<R>(6) * Fx * ux - static_cast<R>(2) * Fu)) *
+               static_cast<R>(1.0 / 36.0);
+  const R a10 = (s_pi * (m10 + half * rho * p9) - k_pi * (Fu - static_cast<R>(3) * Fx * ux)) *
+                static_cast<R>(1.0 / 72.0);
+  const R a11 = (s_nu * (m11 - rho * p11) - k_nu * static_cast<R>(2) * (Fy * uy - Fz * uz)) *
+                static_cast<R>(1.0 / 12.0);
+  const R a12 = (s_pi * (m12 + half * rho * p11) - k_pi * (Fz * uz - Fy * uy)) *
+                static_cast<R>(1.0 / 24.0);
+  const R a13 = (s_nu * (Pxy - rho * ux * uy) - k_nu * (Fx * uy + Fy * ux)) * static_cast<R>(0.25);
+  const R a14 = (s_nu * (Pyz - rho * uy * uz) - k_nu * (Fy * uz + Fz * uy)) * static_cast<R>(0.25);
+  const R a15 = (s_nu * (Pxz - rho * ux * uz) - k_nu * (Fx * uz + Fz * ux)) * static_cast<R>(0.25);
+  const R a16 = s_t * m16 * static_cast<R>(0.125);
+  const R a17 = s_t * m17 * static_cast<R>(0.125);
+  const R a18 = s_t * m18 * static_cast<R>(0.125);
+
+  // f* = f - M^T a
+  d[0] -= static_cast<R>(-30) * a1 + static_cast<R>(12) * a2;
+  const R A = static_cast<R>(-11) * a1 + static_cast<R>(-4) * a2;
+  const R X1 = a3 - static_cast<R>(4) * a4, Y1 = a5 - static_cast<R>(4) * a6,
+          Z1 = a7 - static_cast<R>(4) * a8;
+  const R Pxx = static_cast<R>(2) * a9 - static_cast<R>(4) * a10;
+  const R Pyy = -a9 + static_cast<R>(2) * a10 + a11 - static_cast<R>(2) * a12;
+  const R Pzz = -a9 + static_cast<R>(2) * a10 - a11 + static_cast<R>(2) * a12;
+  d[1] -= A + X1 + Pxx;
+  d[2] -= A - X1 + Pxx;
+  d[3] -= A + Y1 + Pyy;
+  d[4] -= A - Y1 + Pyy;
+  d[5] -= A + Z1 + Pzz;
+  d[6] -= A - Z1 + Pzz;
+  const R D = static_cast<R>(8) * a1 + a2;
+  const R Dxy = D + a9 + a10 + a11 + a12, X2 = a3 + a4 + a16, Y2 = a5 + a6 - a17;
+  d[7] -= Dxy + X2 + Y2 + a13;
+  d[8] -= Dxy - X2 + Y2 - a13;
+  d[9] -= Dxy + X2 - Y2 - a13;
+  d[10] -= Dxy - X2 - Y2 + a13;
+  const R Dxz = D + a9 + a10 - a11 - a12, X3 = a3 + a4 - a16, Z3 = a7 + a8 + a18;
+  d[11] -= Dxz + X3 + Z3 + a15;
+  d[12] -= Dxz - X3 + Z3 - a15;
+  d[13] -= Dxz + X3 - Z3 - a15;
+  d[14] -= Dxz - X3 - Z3 + a15;
+  const R Dyz = D - static_cast<R>(2) * (a9 + a10), Y4 = a5 + a6 + a17, Z4 = a7 + a8 - a18;
+  d[15] -= Dyz + Y4 + Z4 + a14;
+  d[16] -= Dyz - Y4 + Z4 - a14;
+  d[17] -= Dyz + Y4 - Z4 - a14;
+  d[18] -= Dyz - Y4 - Z4 + a14;
+}
+
+// Thermal relaxation rate of a cell: sigma_chi = 1 / tau_g, tau_g = chi / omega_T
+// + 1/2 with chi = lambda(f_l) / (rho0 C_p,ref) (Eq. (20), (34)).
+template <class R>
+__device__ __forceinline__ R sigma_chi(const CavParams& c, R fl) {
+  const R lam = static_cast<R>(c.lam_s) + fl * static_cast<R>(c.lam_l - c.lam_s);
+  return static_cast<R>(1) / (lam * static_cast<R>(c.inv_rcw) + static_cast<R>(0.5));
+}
+
+// MRT rates (Eq. (23), (47)): sigma_1..3 = sigma_chi, sigma_4..6 = 2 - sigma_chi,
+// each replaceable by a fixed override.
+template <class R>
+__device__ __forceinline__ void mrt_rates(const CavParams& c, R sig, R* r) {
+  r[1] = r[2] = r[3] = sig;
+  r[4] = r[5] = r[6] = static_cast<R>(2) - sig;
+  if (c.has_override) {
+#pragma unroll
+    for (int k = 1; k < 7; ++k)
+      if (!isnan(c.sig_ovr[k])) r[k] = static_cast<R>(c.sig_ovr[k]);
+  }
+}
+
+// D3Q7 MRT collision, Eq. (21)-(25).  n_4 - n_4^eq is formed as
+// -7 sum_{a>0} g_a + 21 omega_T C_p,ref T (the g_0 terms cancel exactly), which
+// keeps the latent-heat-sized g_0 out of the difference.
+template <class R>
+__device__ __forceinline__ void enth_collide_mrt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
+                                                 R uy, R uz, R sig) {
+  R r[7];
+  mrt_rates(c, sig, r);
+  const R qT = cp * T;
+  const R b1 = r[1] * (g[1] - g[2] - qT * ux) * static_cast<R>(0.5);
+  const R b2 = r[2] * (g[3] - g[4] - qT * uy) * static_cast<R>(0.5);
+  const R b3 = r[3] * (g[5] - g[6] - qT * uz) * static_cast<R>(0.5);
+  const R b4 = r[4] * (static_cast<R>(-7) * s6 + static_cast<R>(21.0 * c.omega_T * c.cp_ref) * T) *
+               static_cast<R>(1.0 / 42.0);
+  const R g12 = g[1] + g[2], g34 = g[3] + g[4], g56 = g[5] + g[6];
+  const R b5 = r[5] * (static_cast<R>(2) * g12 - (g34 + g56)) * static_cast<R>(1.0 / 12.0);
+  const R b6 = r[6] * (g34 - g56) * static_cast<R>(0.25);
+  g[0] -= static_cast<R>(6) * b4;
+  const R ax = -b4 + static_cast<R>(2) * b5;
+  const R ay = -b4 - b5 + b6;
+  const R az = -b4 - b5 - b6;
+  g[1] -= ax + b1;
+  g[2] -= ax - b1;
+  g[3] -= ay + b2;
+  g[4] -= ay - b2;
+  g[5] -= az + b3;
+  g[6] -= az - b3;
+}
+
+// D3Q7 SRT (BGK) collision, Eq. (5)-(8): g^eq_0 = h - 3 omega_T C_p,ref T,
+// g^eq_a = (omega_T / 2) C_p,ref T + (u.e_a / 2) C_p T.
+template <class R>
+__device__ __forceinline__ void enth_collide_srt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
+                                                 R uy, R uz, R inv_tau) {
+  const R wT = static_cast<R>(0.5 * c.omega_T * c.cp_ref) * T;
+  const R hq = static_cast<R>(0.5) * cp * T;
+  g[0] -= inv_tau * (static_cast<R>(3.0 * c.omega_T * c.cp_ref) * T - s6);
+  g[1] -= inv_tau * (g[1] - (wT + hq * ux));
+  g[2] -= inv_tau * (g[2] - (wT - hq * ux));
+  g[3] -= inv_tau * (g[3] - (wT + hq * uy));
+  g[4] -= inv_tau * (g[4] - (wT - hq * uy));
+  g[5] -= inv_tau * (g[5] - (wT + hq * uz));
+  g[6] -= inv_tau * (g[6] - (wT - hq * uz));
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum NPART values over the workgroup in a fixed order and store them (thread 0).
+__device__ __forceinline__ void block_partials(double* v, double* out, double (*red)[NPART]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) red[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// The fused step
+// ---------------------------------------------------------------------------
+template <int P, bool FLOW, bool MRT, bool BUDGET>
+__global__ void __launch_bounds__(256)
+k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+       const char* __restrict__ src, char* __restrict__ dst, double* __restrict__ partials,
+       const int32_t* __restrict__ status) {
+  using S = typename Fmt<P>::S;
+  using S0 = typename Fmt<P>::S0;
+  using R = typename Fmt<P>::R;
+  __shared__ double red[4][NPART];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int2 tl = tiles[t];
+    const CavParams& c = cavs[tl.x];
+    const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
+    double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (cell < c.n) {
+      const View<P> in = view<P>(src, c, FLOW);
+      const View<P> out = view<P>(dst, c, FLOW);
+      const int64_t pl = c.plane;
+      R d[19];
+      R g[7];
+      if (FLOW) {
+#pragma unroll
+        for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
+      }
+      g[0] = static_cast<R>(in.g0[cell]);
+#pragma unroll
+      for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
+
+      if (status[tl.x]) {  // frozen cavity: keep the state as it is
+        if (FLOW) {
+#pragma unroll
+          for (int a = 0; a < 19; ++a) out.f[a * pl + cell] = enc<S>(d[a]);
+        }
+        out.g0[cell] = static_cast<S0>(g[0]);
+#pragma unroll
+        for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(g[a]);
+      } else {
+        // enthalpy -> (T, f_l) in FP64
+        double s6d = 0.0;
+#pragma unroll
+        for (int a = 1; a < 7; ++a) s6d += static_cast<double>(g[a]);
+        const double hd = static_cast<double>(g[0]) + s6d;
+        double Td, fld;
+        phase_rule(c, hd, Td, fld);
+        const R T = static_cast<R>(Td), fl = static_cast<R>(fld), s6 = static_cast<R>(s6d);
+        const R cp = static_cast<R>(c.cp_s) + fl * static_cast<R>(c.cp_l - c.cp_s);
+        R ux = 0, uy = 0, uz = 0;
+        double rhod = 0.0;
+        bool bad = !isfinite(hd);
+        if (FLOW) {
+          const FlowMacro<R> q = flow_macro<R>(c, d, T, fl);
+          ux = q.ux;
+          uy = q.uy;
+          uz = q.uz;
+          rhod = static_cast<double>(c.fshift) + static_cast<double>(q.dr);
+          bad = bad || !(rhod > 0.5 && rhod < 2.0) || !(ux * ux + uy * uy + uz * uz < R(0.09));
+          flow_collide<R>(c, d, q);
+        }
+        const R sig = sigma_chi<R>(c, fl);
+        if (MRT) enth_collide_mrt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
+        else enth_collide_srt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
+
+        // stream: push every post-collision population along its link
+        const Site s = make_site(c, cell);
+        if (FLOW) {
+          out.f[cell] = enc<S>(d[0]);
+#pragma unroll
+          for (int a = 1; a < 19; ++a) {
+            int face;
+            const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
+            if (face < 0) out.f[a * pl + to] = enc<S>(d[a]);
+            else out.f[Q19OPP[a] * pl + cell] = enc<S>(d[a]);  // halfway bounce-back
+          }
+        }
+        out.g0[cell] = static_cast<S0>(g[0]);
+        double flux = 0.0;
+#pragma unroll
+        for (int a = 1; a < 7; ++a) {
+          int face;
+          const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
+          if (face < 0) {
+            out.g[(a - 1) * pl + to] = enc<S>(g[a]);
+          } else if (c.bc[face] == BC_DIRICHLET) {
+            // anti-bounce-back: g_abar(x) = -g*_a(x) + 2 w C_p,ref T_w
+            const double Tw = c.tw[c.twface[face] + face_node(c, s, face)];
+            const R back = -g[a] + static_cast<R>(c.omega_T * c.cp_ref) * static_cast<R>(Tw);
+            out.g[(Q7OPP[a] - 1) * pl + cell] = enc<S>(back);
+            flux += static_cast<double>(back) - static_cast<double>(g[a]);
+          } else {
+            out.g[(Q7OPP[a] - 1) * pl + cell] = enc<S>(g[a]);  // adiabatic
+          }
+        }
+        acc[0] = hd;
+        acc[1] = rhod;
+        acc[2] = fld;
+        acc[3] = flux;
+        acc[4] = bad ? 1.0 : 0.0;
+      }
+    }
+    if (BUDGET) block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
+  }
+}
+
+// Initial state at rest: f = w rho0 (stored deviation 0 in shifted formats),
+// g = g^eq(h0(T0), T0, u = 0) with h0 from Eq. (2).
+template <int P, bool FLOW>
+__global__ void __launch_bounds__(256)
+k_init(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+       char* __restrict__ dst, const double* __restrict__ T0) {
+  using S = typename Fmt<P>::S;
+  using S0 = typename Fmt<P>::S0;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int2 tl = tiles[t];
+    const CavParams& c = cavs[tl.x];
+    const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
+    if (cell >= c.n) continue;
+    const View<P> out = view<P>(dst, c, FLOW);
+    const int64_t pl = c.plane;
+    if (FLOW) {
+#pragma unroll
+      for (int a = 0; a < 19; ++a)
+        out.f[a * pl + cell] = enc<S>(W19[a] * (c.rho0 - c.fshift));
+    }
+    const double T = T0 ? T0[c.cell_off + cell] : c.T_m;
+    const double h0 = T <= c.T_m ? c.cp_s * T : c.cp_l * T + c.latent;
+    out.g0[cell] = static_cast<S0>(h0 - 3.0 * c.omega_T * c.cp_ref * T);
+    const double ga = 0.5 * c.omega_T * c.cp_ref * T;
+#pragma unroll
+    for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(ga);
+  }
+}
+
+// Sums of the current state per tile: h, rho, f_l (flux 0, bad-cell count).
+template <int P, bool FLOW>
+__global__ void __launch_bounds__(256)
+k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+          const char* __restrict__ src, double* __restrict__ partials) {
+  __shared__ double red[4][NPART];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int2 tl = tiles[t];
+    const CavParams& c = cavs[tl.x];
+    const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
+    double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (cell < c.n) {
+      const View<P> in = view<P>(src, c, FLOW);
+      const int64_t pl = c.plane;
+      double h = static_cast<double>(in.g0[cell]);
+#pragma unroll
+      for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+      double T, fl;
+      phase_rule(c, h, T, fl);
+      double rho = 0.0;
+      if (FLOW) {
+        rho = c.fshift;
+        double dr = 0.0;
+#pragma unroll
+        for (int a = 0; a < 19; ++a) dr += static_cast<double>(dec(in.f[a * pl + cell]));
+        rho += dr;
+      }
+      acc[0] = h;
+      acc[1] = rho;
+      acc[2] = fl;
+      acc[4] = isfinite(h) && isfinite(rho) ? 0.0 : 1.0;
+    }
+    block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
+  }
+}
+
+// Fields of one cavity (FP64 planes in mask-bit order: h, T, f_l, rho, u).
+template <int P, bool FLOW>
+__global__ void __launch_bounds__(256)
+k_fields(const CavParams* __restrict__ cavp, const char* __restrict__ src, uint32_t mask,
+         double* __restrict__ out) {
+  using R = typename Fmt<P>::R;
+  const CavParams& c = *cavp;
+  const int32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= c.n) return;
+  const View<P> in = view<P>(src, c, FLOW);
+  const int64_t pl = c.plane;
+  double h = static_cast<double>(in.g0[cell]);
+#pragma unroll
+  for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+  double T, fl;
+  phase_rule(c, h, T, fl);
+  double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
+  if (FLOW) {
+    R d[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
+    const FlowMacro<R> q = flow_macro<R>(c, d, static_cast<R>(T), static_cast<R>(fl));
+    rho = static_cast<double>(c.fshift) + static_cast<double>(q.dr);
+    u[0] = q.ux;
+    u[1] = q.uy;
+    u[2] = q.uz;
+  }
+  int64_t k = 0;
+  const int64_t n = c.n;
+  if (mask & 1u) out[(k++) * n + cell] = h;
+  if (mask & 2u) out[(k++) * n + cell] = T;
+  if (mask & 4u) out[(k++) * n + cell] = fl;
+  if (mask & 8u) out[(k++) * n + cell] = rho;
+  if (mask & 16u) {
+    out[(k++) * n + cell] = u[0];
+    out[(k++) * n + cell] = u[1];
+    out[(k++) * n + cell] = u[2];
+  }
+}
+
+template <int P, bool FLOW>
+__global__ void __launch_bounds__(256)
+k_get_state(const CavParams* __restrict__ cavp, const char* __restrict__ src,
+            double* __restrict__ f, double* __restrict__ g) {
+  const CavParams& c = *cavp;
+  const int32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= c.n) return;
+  const View<P> in = view<P>(src, c, FLOW);
+  const int64_t pl = c.plane, n = c.n;
+  if (FLOW && f) {
+#pragma unroll
+    for (int a = 0; a < 19; ++a)
+      f[a * n + cell] = static_cast<double>(dec(in.f[a * pl + cell])) + W19[a] * c.fshift;
+  }
+  g[cell] = static_cast<double>(in.g0[cell]);
+#pragma unroll
+  for (int a = 1; a < 7; ++a) g[a * n + cell] = static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+}
+
+template <int P, bool FLOW>
+__global__ void __launch_bounds__(256)
+k_set_state(const CavParams* __restrict__ cavp, char* __restrict__ dst,
+            const double* __restrict__ f, const double* __restrict__ g) {
+  using S = typename Fmt<P>::S;
+  using S0 = typename Fmt<P>::S0;
+  const CavParams& c = *cavp;
+  const int32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= c.n) return;
+  const View<P> out = view<P>(dst, c, FLOW);
+  const int64_t pl = c.plane, n = c.n;
+  if (FLOW) {
+#pragma unroll
+    for (int a = 0; a < 19; ++a) out.f[a * pl + cell] = enc<S>(f[a * n + cell] - W19[a] * c.fshift);
+  }
+  out.g0[cell] = static_cast<S0>(g[cell]);
+#pragma unroll
+  for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(g[a * n + cell]);
+}
+
+}  // namespace lbpc

@@ -1,0 +1,121 @@
+// Host-side launchers of the per-format kernels.  Each kernel translation unit
+// includes this file once and instantiates the launchers for one format.
+#pragma once
+#include "lbpc_adjoint.hpp"
+#include "lbpc_device.hpp"
+
+namespace lbpc {
+
+inline dim3 cell_grid(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
+
+template <int P>
+hipError_t launch_step(const StepArgs& a) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 grid(a.grid > 0 ? (a.grid < a.ntiles ? a.grid : a.ntiles) : a.ntiles);
+  const dim3 block(a.block);
+#define LBPC_STEP(FL, MR, BU)                                                              \
+  hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
+                     a.ntiles, a.src, a.dst, a.partials, a.status)
+  const bool bu = a.partials != nullptr;
+  if (a.flow) {
+    if (a.mrt) { if (bu) LBPC_STEP(true, true, true); else LBPC_STEP(true, true, false); }
+    else { if (bu) LBPC_STEP(true, false, true); else LBPC_STEP(true, false, false); }
+  } else {
+    if (a.mrt) { if (bu) LBPC_STEP(false, true, true); else LBPC_STEP(false, true, false); }
+    else { if (bu) LBPC_STEP(false, false, true); else LBPC_STEP(false, false, false); }
+  }
+#undef LBPC_STEP
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_init(const CavParams* cavs, const int2* tiles, int ntiles, int block, int flow,
+                       char* dst, const double* T0, hipStream_t st) {
+  if (flow)
+    hipLaunchKernelGGL((k_init<P, true>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, dst, T0);
+  else
+    hipLaunchKernelGGL((k_init<P, false>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, dst, T0);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_measure(const CavParams* cavs, const int2* tiles, int ntiles, int block,
+                          int flow, const char* src, double* partials, hipStream_t st) {
+  if (flow)
+    hipLaunchKernelGGL((k_measure<P, true>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, src, partials);
+  else
+    hipLaunchKernelGGL((k_measure<P, false>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, src, partials);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_fields(const CavParams* cav, int64_t n, int flow, const char* src,
+                         uint32_t mask, double* out, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_fields<P, true>), cell_grid(n), dim3(256), 0, st, cav, src, mask, out);
+  else hipLaunchKernelGGL((k_fields<P, false>), cell_grid(n), dim3(256), 0, st, cav, src, mask, out);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_get_state(const CavParams* cav, int64_t n, int flow, const char* src,
+                            double* f, double* g, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_get_state<P, true>), cell_grid(n), dim3(256), 0, st, cav, src, f, g);
+  else hipLaunchKernelGGL((k_get_state<P, false>), cell_grid(n), dim3(256), 0, st, cav, src, f, g);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_set_state(const CavParams* cav, int64_t n, int flow, char* dst,
+                            const double* f, const double* g, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_set_state<P, true>), cell_grid(n), dim3(256), 0, st, cav, dst, f, g);
+  else hipLaunchKernelGGL((k_set_state<P, false>), cell_grid(n), dim3(256), 0, st, cav, dst, f, g);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_adjoint(const AdjArgs& a) {
+  const dim3 grid(a.ntiles), block(a.block);
+#define LBPC_ADJ(FL, MR)                                                                    \
+  hipLaunchKernelGGL((k_adjoint<P, FL, MR>), grid, block, 0, a.stream, a.cavs, a.tiles,    \
+                     a.ntiles, a.state, a.lam_in, a.lam_out, a.dTw)
+  if (a.flow) { if (a.mrt) LBPC_ADJ(true, true); else LBPC_ADJ(true, false); }
+  else { if (a.mrt) LBPC_ADJ(false, true); else LBPC_ADJ(false, false); }
+#undef LBPC_ADJ
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_adj_seed(const CavParams* cav, int64_t n, int flow, double scale,
+                           const char* state, char* lam, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_adj_seed<P, true>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale);
+  else hipLaunchKernelGGL((k_adj_seed<P, false>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int flow, const char* state0,
+                         const char* lam, double* out, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_adj_T0<P, true>), cell_grid(n), dim3(256), 0, st, cav, state0, lam, out);
+  else hipLaunchKernelGGL((k_adj_T0<P, false>), cell_grid(n), dim3(256), 0, st, cav, state0, lam, out);
+  return hipGetLastError();
+}
+
+#define LBPC_INSTANTIATE(P)                                                                       \
+  template hipError_t launch_step<P>(const StepArgs&);                                            \
+  template hipError_t launch_init<P>(const CavParams*, const int2*, int, int, int, char*,         \
+                                     const double*, hipStream_t);                                 \
+  template hipError_t launch_measure<P>(const CavParams*, const int2*, int, int, int,             \
+                                        const char*, double*, hipStream_t);                       \
+  template hipError_t launch_fields<P>(const CavParams*, int64_t, int, const char*, uint32_t,     \
+                                       double*, hipStream_t);                                     \
+  template hipError_t launch_get_state<P>(const CavParams*, int64_t, int, const char*, double*,   \
+                                          double*, hipStream_t);                                  \
+  template hipError_t launch_set_state<P>(const CavParams*, int64_t, int, char*, const double*,   \
+                                          const double*, hipStream_t);                            \
+  template hipError_t launch_adjoint<P>(const AdjArgs&);                                          \
+  template hipError_t launch_adj_seed<P>(const CavParams*, int64_t, int, double, const char*,     \
+                                         char*, hipStream_t);                                     \
+  template hipError_t launch_adj_T0<P>(const CavParams*, int64_t, int, const char*, const char*,  \
+                                       double*, hipStream_t);
+
+}  // namespace lbpc

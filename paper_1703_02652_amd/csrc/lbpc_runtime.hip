@@ -1,0 +1,952 @@
+// Runtime behind the lbpc C ABI: validation, workspace layout, tile queue,
+// HIP graphs, budgets, launch-shape autotuning, checkpoints and the
+// checkpointed discrete adjoint.  All device memory comes from the caller.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbpc.h"
+#include "lbpc_api.hpp"
+
+using namespace lbpc;
+
+namespace {
+
+constexpr int kRing = 16;           // budget partial slots (steps between reductions)
+constexpr int kMinTile = 64;        // smallest tile: one wavefront
+constexpr int kMaxTile = 256;       // largest tile: __launch_bounds__ of the kernels
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------
+// Kernels that do not depend on the storage format
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_reduce(const CavParams* __restrict__ cavs, const double* __restrict__ partials,
+         int64_t slot_stride, int nslots, int mode, BudgetRec* __restrict__ rec,
+         int32_t* __restrict__ status) {
+  __shared__ double sh[256][NPART];
+  const CavParams& c = cavs[blockIdx.x];
+  for (int s = 0; s < nslots; ++s) {
+    double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const double* p = partials + static_cast<int64_t>(s) * slot_stride * NPART;
+    for (int t = threadIdx.x; t < c.ntiles; t += blockDim.x) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) v[k] += p[static_cast<int64_t>(c.tile0 + t) * NPART + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (static_cast<int>(threadIdx.x) < w) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + w][k];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      BudgetRec& r = rec[blockIdx.x];
+      if (mode == 0) {
+        r.H = sh[0][0];
+        r.mass = sh[0][1];
+        r.fl = sh[0][2];
+        r.flux_last = sh[0][3];
+        r.flux_cum += sh[0][3];
+        r.steps += 1.0;
+      } else {
+        r.now_H = sh[0][0];
+        r.now_mass = sh[0][1];
+        r.now_fl = sh[0][2];
+      }
+      if (sh[0][4] > 0.0 || !isfinite(sh[0][0]) || !isfinite(sh[0][1])) status[blockIdx.x] = 1;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t nwords) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nwords;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Layout
+// ---------------------------------------------------------------------------
+struct Layout {
+  int batch = 0, prec = 0, flow = 0, mrt = 0;
+  std::vector<int64_t> ncell, off, plane, cell_off, tw_off;
+  std::vector<std::array<int64_t, 6>> twface;
+  int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, tw_doubles = 0;
+  size_t o_params = 0, o_tiles = 0, o_tw = 0, o_status = 0, o_rec = 0, o_part = 0,
+         o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
+};
+
+size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
+size_t g0_bytes(int prec) { return prec == 0 ? 8 : 4; }
+
+int64_t face_size(const lbpc_config& c, int face) {
+  const int d = face / 2;
+  if (d == 0) return static_cast<int64_t>(c.ny) * c.nz;
+  if (d == 1) return static_cast<int64_t>(c.nx) * c.nz;
+  return static_cast<int64_t>(c.nx) * c.ny;
+}
+
+bool validate(const lbpc_config* cfgs, int batch, std::string& err) {
+  char buf[256];
+  if (!cfgs || batch < 1) {
+    err = "cfgs must hold at least one cavity";
+    return false;
+  }
+  int64_t total = 0;
+  for (int i = 0; i < batch; ++i) {
+    const lbpc_config& c = cfgs[i];
+    auto bad = [&](const char* what) {
+      std::snprintf(buf, sizeof(buf), "cavity %d: %s", i, what);
+      err = buf;
+      return false;
+    };
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) return bad("nx, ny, nz must be >= 1");
+    const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
+    if (n >= (int64_t(1) << 30)) return bad("too many cells (limit 2^30 per cavity)");
+    total += n;
+    if (c.flow != 0 && c.flow != 1) return bad("flow must be 0 or 1");
+    if (c.enth_model != LBPC_SRT && c.enth_model != LBPC_MRT) return bad("enth_model must be SRT or MRT");
+    if (c.precision < 0 || c.precision > 3) return bad("unknown precision");
+    if (c.precision != cfgs[0].precision || c.flow != cfgs[0].flow ||
+        c.enth_model != cfgs[0].enth_model)
+      return bad("precision, flow and enth_model must be the same for the whole batch");
+    for (int f = 0; f < 6; ++f) {
+      if (c.face_bc[f] < 0 || c.face_bc[f] > 2) return bad("unknown face boundary type");
+      if (!std::isfinite(c.face_T[f])) return bad("face_T must be finite");
+    }
+    for (int d = 0; d < 3; ++d)
+      if ((c.face_bc[2 * d] == LBPC_PERIODIC) != (c.face_bc[2 * d + 1] == LBPC_PERIODIC))
+        return bad("a periodic face needs a periodic partner");
+    if (!(c.omega_T > 0.0 && c.omega_T <= 1.0 / 3.0)) return bad("omega_T must lie in (0, 1/3]");
+    if (!(c.cp_s > 0 && c.cp_l > 0 && c.cp_ref > 0)) return bad("specific heats must be > 0");
+    if (!(c.lambda_s > 0 && c.lambda_l > 0)) return bad("conductivities must be > 0");
+    if (!(c.rho0 > 0)) return bad("rho0 must be > 0");
+    if (!std::isfinite(c.T_m) || !std::isfinite(c.T_ref) || !std::isfinite(c.g_beta))
+      return bad("T_m, T_ref and g_beta must be finite");
+    if (!(c.cp_l * c.T_m + c.latent > c.cp_s * c.T_m)) return bad("h_l must exceed h_s");
+    if (c.flow) {
+      if (!(c.nu > 0)) return bad("nu must be > 0");
+      const double r[5] = {c.s_e, c.s_eps, c.s_q, c.s_pi, c.s_t};
+      for (double v : r)
+        if (!(v > 0.0 && v < 2.0)) return bad("flow relaxation rates must lie in (0, 2)");
+    }
+    for (int k = 0; k < 7; ++k) {
+      const double v = c.sigma_override[k];
+      if (!std::isnan(v) && !(v > 0.0 && v < 2.0)) return bad("sigma_override entries must be NaN or in (0, 2)");
+    }
+  }
+  if (total >= (int64_t(1) << 31)) {
+    err = "too many cells in the batch";
+    return false;
+  }
+  return true;
+}
+
+Layout make_layout(const lbpc_config* cfgs, int batch) {
+  Layout L;
+  L.batch = batch;
+  L.prec = cfgs[0].precision;
+  L.flow = cfgs[0].flow;
+  L.mrt = cfgs[0].enth_model;
+  const size_t pb = pop_bytes(L.prec), g0b = g0_bytes(L.prec);
+  int64_t off = 0, cells = 0, tiles = 0, tw = 0;
+  for (int i = 0; i < batch; ++i) {
+    const lbpc_config& c = cfgs[i];
+    const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
+    const int64_t plane = (n + 127) / 128 * 128;
+    L.ncell.push_back(n);
+    L.plane.push_back(plane);
+    L.off.push_back(off);
+    L.cell_off.push_back(cells);
+    const size_t bytes = static_cast<size_t>(plane) * ((L.flow ? 19 : 0) + 6) * pb +
+                         static_cast<size_t>(plane) * g0b;
+    off += static_cast<int64_t>(align_up(bytes));
+    cells += n;
+    tiles += (n + kMinTile - 1) / kMinTile;
+    std::array<int64_t, 6> tf;
+    int64_t fo = 0;
+    for (int f = 0; f < 6; ++f) {
+      tf[f] = fo;
+      fo += face_size(c, f);
+    }
+    L.twface.push_back(tf);
+    L.tw_off.push_back(tw);
+    tw += fo;
+  }
+  L.region_bytes = off;
+  L.total_cells = cells;
+  L.max_tiles = tiles;
+  L.tw_doubles = tw;
+  size_t o = 0;
+  L.o_params = o; o = align_up(o + sizeof(CavParams) * batch);
+  L.o_tiles = o; o = align_up(o + sizeof(int2) * tiles);
+  L.o_tw = o; o = align_up(o + sizeof(double) * tw);
+  L.o_status = o; o = align_up(o + sizeof(int32_t) * batch);
+  L.o_rec = o; o = align_up(o + sizeof(BudgetRec) * batch);
+  L.o_part = o; o = align_up(o + sizeof(double) * NPART * tiles * kRing);
+  L.o_mpart = o; o = align_up(o + sizeof(double) * NPART * tiles);
+  L.o_region0 = o; o = align_up(o + L.region_bytes);
+  L.o_region1 = o; o = align_up(o + L.region_bytes);
+  L.total = o;
+  return L;
+}
+
+// Multiplier and shift for q = (i * m) >> s == i / d, exact for i < 2^31:
+// m = floor(2^(32+l) / d) + 1 with l = ceil(log2 d).
+void magic(uint32_t d, uint64_t& m, uint32_t& s) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  m = (uint64_t(1) << (32 + l)) / d + 1;
+  s = 32 + l;
+}
+
+CavParams make_params(const lbpc_config& c, const Layout& L, int i, const double* d_tw) {
+  CavParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.nx = c.nx;
+  p.ny = c.ny;
+  p.nz = c.nz;
+  p.n = static_cast<int32_t>(L.ncell[i]);
+  p.nxy = c.nx * c.ny;
+  for (int f = 0; f < 6; ++f) p.bc[f] = c.face_bc[f];
+  magic(static_cast<uint32_t>(c.nx), p.div_nx_m, p.div_nx_s);
+  magic(static_cast<uint32_t>(p.nxy), p.div_nxy_m, p.div_nxy_s);
+  p.off = L.off[i];
+  p.plane = L.plane[i];
+  p.cell_off = L.cell_off[i];
+  p.tw = d_tw + L.tw_off[i];
+  for (int f = 0; f < 6; ++f) p.twface[f] = L.twface[i][f];
+  p.omega_T = c.omega_T;
+  p.cp_s = c.cp_s;
+  p.cp_l = c.cp_l;
+  p.cp_ref = c.cp_ref;
+  p.lam_s = c.lambda_s;
+  p.lam_l = c.lambda_l;
+  p.latent = c.latent;
+  p.T_m = c.T_m;
+  p.rho0 = c.rho0;
+  p.hs = c.cp_s * c.T_m;
+  p.hl = c.cp_l * c.T_m + c.latent;
+  p.inv_dh = 1.0 / (p.hl - p.hs);
+  p.inv_cps = 1.0 / c.cp_s;
+  p.inv_cpl = 1.0 / c.cp_l;
+  p.inv_rcw = 1.0 / (c.rho0 * c.cp_ref * c.omega_T);
+  p.has_override = 0;
+  for (int k = 0; k < 7; ++k) {
+    p.sig_ovr[k] = c.sigma_override[k];
+    if (!std::isnan(c.sigma_override[k])) p.has_override = 1;
+  }
+  p.s_nu = 1.0 / (3.0 * c.nu + 0.5);  // Eq. (59)
+  p.s_e = c.s_e;
+  p.s_eps = c.s_eps;
+  p.s_q = c.s_q;
+  p.s_pi = c.s_pi;
+  p.s_t = c.s_t;
+  p.g_beta_rho0 = c.g_beta * c.rho0;
+  p.T_ref = c.T_ref;
+  p.fshift = c.precision == LBPC_FP64 ? 0.0 : c.rho0;
+  return p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct AdjointPlan {
+  bool ready = false;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  int64_t nsteps = 0, end_step = 0;
+  int32_t every = 0, loss = 0;
+  int nsnap = 0;
+  size_t o_snap = 0, o_seg = 0, o_lam0 = 0, o_lam1 = 0, o_dtw = 0, o_part = 0, total = 0;
+  size_t lam_bytes = 0;
+};
+
+struct lbpc_ctx {
+  Layout L;
+  std::vector<lbpc_config> cfg;
+  std::vector<CavParams> hp;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  char* ws = nullptr;
+  CavParams* d_params = nullptr;
+  int2* d_tiles = nullptr;
+  double* d_tw = nullptr;
+  int32_t* d_status = nullptr;
+  BudgetRec* d_rec = nullptr;
+  double* d_part = nullptr;
+  double* d_mpart = nullptr;
+  char* region[2] = {nullptr, nullptr};
+  int cur = 0;
+  int block = 256, grid = 0, graph_steps = 16;
+  int ntiles = 0;
+  int pending = 0;
+  int64_t steps = 0;
+  bool unstable = false;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  std::string err;
+  AdjointPlan adj;
+};
+
+namespace {
+
+int fail(lbpc_ctx* x, int code, const std::string& msg) {
+  if (x) x->err = msg;
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x, call)                                                                 \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((x), LBPC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials,
+                         hipStream_t st) {
+  StepArgs a;
+  a.cavs = x->d_params;
+  a.tiles = x->d_tiles;
+  a.ntiles = x->ntiles;
+  a.src = src;
+  a.dst = dst;
+  a.partials = partials;
+  a.status = x->d_status;
+  a.block = x->block;
+  a.grid = x->grid;
+  a.flow = x->L.flow;
+  a.mrt = x->L.mrt;
+  a.stream = st;
+  switch (x->L.prec) {
+    case 0: return launch_step<0>(a);
+    case 1: return launch_step<1>(a);
+    case 2: return launch_step<2>(a);
+    default: return launch_step<3>(a);
+  }
+}
+
+hipError_t dispatch_measure(lbpc_ctx* x, const char* src, double* partials) {
+  switch (x->L.prec) {
+    case 0: return launch_measure<0>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
+    case 1: return launch_measure<1>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
+    case 2: return launch_measure<2>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
+    default: return launch_measure<3>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
+  }
+}
+
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>(bytes / 4);
+  if (words == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_zero, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(x->L.batch), dim3(256), 0, st, x->d_params, partials,
+                     static_cast<int64_t>(x->L.max_tiles), nslots, mode, x->d_rec, x->d_status);
+  return hipGetLastError();
+}
+
+void drop_graphs(lbpc_ctx* x) {
+  for (int i = 0; i < 2; ++i) {
+    if (x->gexec[i]) hipGraphExecDestroy(x->gexec[i]);
+    if (x->graph[i]) hipGraphDestroy(x->graph[i]);
+    x->gexec[i] = nullptr;
+    x->graph[i] = nullptr;
+  }
+}
+
+// Tile queue for the current block size: tiles never straddle cavities.
+int build_tiles(lbpc_ctx* x) {
+  std::vector<int2> tiles;
+  for (int i = 0; i < x->L.batch; ++i) {
+    x->hp[i].tile0 = static_cast<int32_t>(tiles.size());
+    const int64_t n = x->L.ncell[i];
+    for (int64_t c0 = 0; c0 < n; c0 += x->block) tiles.push_back(make_int2(i, static_cast<int>(c0)));
+    x->hp[i].ntiles = static_cast<int32_t>(tiles.size()) - x->hp[i].tile0;
+  }
+  x->ntiles = static_cast<int>(tiles.size());
+  HIPCHK(x, hipMemcpyAsync(x->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                           hipMemcpyHostToDevice, x->stream));
+  HIPCHK(x, hipMemcpyAsync(x->d_params, x->hp.data(), sizeof(CavParams) * x->hp.size(),
+                           hipMemcpyHostToDevice, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  drop_graphs(x);
+  return LBPC_OK;
+}
+
+int flush(lbpc_ctx* x) {
+  if (x->pending > 0) {
+    HIPCHK(x, reduce(x, x->d_part, x->pending, 0, x->stream));
+    x->pending = 0;
+  }
+  return LBPC_OK;
+}
+
+// One eager step: partials into the next ring slot, reduction when the ring fills.
+int eager_step(lbpc_ctx* x) {
+  double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * NPART;
+  HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, x->stream));
+  x->cur ^= 1;
+  x->steps += 1;
+  if (++x->pending == kRing) return flush(x);
+  return LBPC_OK;
+}
+
+// Capture graph_steps steps plus their reduction, starting from region `from`.
+int capture(lbpc_ctx* x, int from) {
+  HIPCHK(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
+  int c = from;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < x->graph_steps && e == hipSuccess; ++i) {
+    double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_tiles * NPART;
+    e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, x->cap);
+    c ^= 1;
+  }
+  if (e == hipSuccess) e = reduce(x, x->d_part, x->graph_steps, 0, x->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(x->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(x, LBPC_EHIP, std::string("graph capture: ") +
+                                  hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  x->graph[from] = g;
+  HIPCHK(x, hipGraphInstantiate(&x->gexec[from], g, nullptr, nullptr, 0));
+  return LBPC_OK;
+}
+
+int run_steps(lbpc_ctx* x, int64_t n) {
+  while (n > 0) {
+    if (x->graph_steps > 0 && x->pending == 0 && n >= x->graph_steps) {
+      if (!x->gexec[x->cur]) {
+        const int rc = capture(x, x->cur);
+        if (rc) return rc;
+      }
+      HIPCHK(x, hipGraphLaunch(x->gexec[x->cur], x->stream));
+      x->steps += x->graph_steps;
+      n -= x->graph_steps;
+    } else {
+      const int rc = eager_step(x);
+      if (rc) return rc;
+      n -= 1;
+    }
+  }
+  return LBPC_OK;
+}
+
+int check_cavity(lbpc_ctx* x, int cavity) {
+  if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
+  if (cavity < 0 || cavity >= x->L.batch) return fail(x, LBPC_EINVAL, "cavity index out of range");
+  return LBPC_OK;
+}
+
+int read_status(lbpc_ctx* x, std::vector<int32_t>& st) {
+  st.resize(x->L.batch);
+  HIPCHK(x, hipMemcpyAsync(st.data(), x->d_status, sizeof(int32_t) * st.size(),
+                           hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  for (int32_t v : st)
+    if (v) x->unstable = true;
+  return LBPC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* lbpc_version(void) { return "lbpc 0.1 (gfx950)"; }
+
+const char* lbpc_last_error(const lbpc_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+size_t lbpc_workspace_bytes(const lbpc_config* cfgs, int32_t batch) {
+  std::string err;
+  if (!validate(cfgs, batch, err)) {
+    g_err = err;
+    return 0;
+  }
+  return make_layout(cfgs, batch).total;
+}
+
+int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, size_t bytes,
+                const double* dev_T0, void* hip_stream, lbpc_ctx** out) {
+  if (!out) return fail(nullptr, LBPC_EINVAL, "out must not be null");
+  *out = nullptr;
+  std::string err;
+  if (!validate(cfgs, batch, err)) return fail(nullptr, LBPC_EINVAL, err);
+  Layout L = make_layout(cfgs, batch);
+  if (!dev_workspace) return fail(nullptr, LBPC_EINVAL, "workspace must not be null");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
+    return fail(nullptr, LBPC_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total) return fail(nullptr, LBPC_ENOSPACE, "workspace too small");
+  lbpc_ctx* x = new lbpc_ctx;
+  x->L = L;
+  x->cfg.assign(cfgs, cfgs + batch);
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  x->ws = static_cast<char*>(dev_workspace);
+  x->d_params = reinterpret_cast<CavParams*>(x->ws + L.o_params);
+  x->d_tiles = reinterpret_cast<int2*>(x->ws + L.o_tiles);
+  x->d_tw = reinterpret_cast<double*>(x->ws + L.o_tw);
+  x->d_status = reinterpret_cast<int32_t*>(x->ws + L.o_status);
+  x->d_rec = reinterpret_cast<BudgetRec*>(x->ws + L.o_rec);
+  x->d_part = reinterpret_cast<double*>(x->ws + L.o_part);
+  x->d_mpart = reinterpret_cast<double*>(x->ws + L.o_mpart);
+  x->region[0] = x->ws + L.o_region0;
+  x->region[1] = x->ws + L.o_region1;
+  for (int i = 0; i < batch; ++i) x->hp.push_back(make_params(cfgs[i], L, i, x->d_tw));
+  auto cleanup = [&](int rc) {
+    if (rc != LBPC_OK) {
+      if (x->cap) hipStreamDestroy(x->cap);
+      delete x;
+    }
+    return rc;
+  };
+  if (hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(nullptr, LBPC_EHIP, "hipStreamCreate failed"));
+  // wall fields start at the constant face temperatures
+  std::vector<double> tw(static_cast<size_t>(L.tw_doubles));
+  for (int i = 0; i < batch; ++i)
+    for (int f = 0; f < 6; ++f) {
+      const int64_t o = L.tw_off[i] + L.twface[i][f];
+      std::fill(tw.begin() + o, tw.begin() + o + face_size(cfgs[i], f), cfgs[i].face_T[f]);
+    }
+  if (hipMemcpyAsync(x->d_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice,
+                     x->stream) != hipSuccess ||
+      fill_zero(x->d_status, sizeof(int32_t) * batch, x->stream) != hipSuccess ||
+      fill_zero(x->d_rec, sizeof(BudgetRec) * batch, x->stream) != hipSuccess)
+    return cleanup(fail(nullptr, LBPC_EHIP, "workspace initialisation failed"));
+  int rc = build_tiles(x);
+  if (rc) return cleanup(fail(nullptr, rc, x->err));
+  hipError_t e;
+  switch (L.prec) {
+    case 0: e = launch_init<0>(x->d_params, x->d_tiles, x->ntiles, x->block, L.flow, x->region[0], dev_T0, x->stream); break;
+    case 1: e = launch_init<1>(x->d_params, x->d_tiles, x->ntiles, x->block, L.flow, x->region[0], dev_T0, x->stream); break;
+    case 2: e = launch_init<2>(x->d_params, x->d_tiles, x->ntiles, x->block, L.flow, x->region[0], dev_T0, x->stream); break;
+    default: e = launch_init<3>(x->d_params, x->d_tiles, x->ntiles, x->block, L.flow, x->region[0], dev_T0, x->stream); break;
+  }
+  if (e != hipSuccess) return cleanup(fail(nullptr, LBPC_EHIP, hipGetErrorString(e)));
+  if (hipStreamSynchronize(x->stream) != hipSuccess)
+    return cleanup(fail(nullptr, LBPC_EHIP, "initialisation failed"));
+  *out = x;
+  return LBPC_OK;
+}
+
+void lbpc_destroy(lbpc_ctx* x) {
+  if (!x) return;
+  if (x->stream) hipStreamSynchronize(x->stream);
+  drop_graphs(x);
+  if (x->cap) hipStreamDestroy(x->cap);
+  delete x;
+}
+
+int lbpc_set_wall_T(lbpc_ctx* x, int32_t cavity, int32_t face, const double* dev_Tw) {
+  int rc = check_cavity(x, cavity);
+  if (rc) return rc;
+  if (face < 0 || face > 5 || !dev_Tw) return fail(x, LBPC_EINVAL, "bad face or null field");
+  if (x->cfg[cavity].face_bc[face] != LBPC_DIRICHLET)
+    return fail(x, LBPC_EINVAL, "face is not a fixed-temperature face");
+  double* dst = x->d_tw + x->L.tw_off[cavity] + x->L.twface[cavity][face];
+  HIPCHK(x, hipMemcpyAsync(dst, dev_Tw, sizeof(double) * face_size(x->cfg[cavity], face),
+                           hipMemcpyDeviceToDevice, x->stream));
+  return LBPC_OK;
+}
+
+int lbpc_step(lbpc_ctx* x, int64_t nsteps) {
+  if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
+  if (nsteps < 0) return fail(x, LBPC_EINVAL, "nsteps must be >= 0");
+  if (x->unstable) return fail(x, LBPC_EUNSTABLE, "a cavity was flagged unstable");
+  return run_steps(x, nsteps);
+}
+
+int lbpc_fields(lbpc_ctx* x, int32_t cavity, uint32_t mask, double* dev_out) {
+  int rc = check_cavity(x, cavity);
+  if (rc) return rc;
+  if (!dev_out || mask == 0 || mask > 31) return fail(x, LBPC_EINVAL, "bad mask or null output");
+  const CavParams* cp = x->d_params + cavity;
+  const int64_t n = x->L.ncell[cavity];
+  hipError_t e;
+  switch (x->L.prec) {
+    case 0: e = launch_fields<0>(cp, n, x->L.flow, x->region[x->cur], mask, dev_out, x->stream); break;
+    case 1: e = launch_fields<1>(cp, n, x->L.flow, x->region[x->cur], mask, dev_out, x->stream); break;
+    case 2: e = launch_fields<2>(cp, n, x->L.flow, x->region[x->cur], mask, dev_out, x->stream); break;
+    default: e = launch_fields<3>(cp, n, x->L.flow, x->region[x->cur], mask, dev_out, x->stream); break;
+  }
+  HIPCHK(x, e);
+  return LBPC_OK;
+}
+
+int lbpc_budgets(lbpc_ctx* x, double* host_out) {
+  if (!x || !host_out) return fail(x, LBPC_EINVAL, "null argument");
+  int rc = flush(x);
+  if (rc) return rc;
+  HIPCHK(x, dispatch_measure(x, x->region[x->cur], x->d_mpart));
+  HIPCHK(x, reduce(x, x->d_mpart, 1, 1, x->stream));
+  std::vector<BudgetRec> rec(x->L.batch);
+  HIPCHK(x, hipMemcpyAsync(rec.data(), x->d_rec, sizeof(BudgetRec) * rec.size(),
+                           hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  for (int i = 0; i < x->L.batch; ++i) {
+    host_out[5 * i + 0] = rec[i].now_H;
+    host_out[5 * i + 1] = rec[i].now_mass;
+    host_out[5 * i + 2] = rec[i].now_fl;
+    host_out[5 * i + 3] = rec[i].flux_cum;
+    host_out[5 * i + 4] = static_cast<double>(x->steps);
+  }
+  std::vector<int32_t> st;
+  return read_status(x, st);
+}
+
+int lbpc_status(lbpc_ctx* x, int32_t* host_flags) {
+  if (!x || !host_flags) return fail(x, LBPC_EINVAL, "null argument");
+  int rc = flush(x);
+  if (rc) return rc;
+  std::vector<int32_t> st;
+  rc = read_status(x, st);
+  if (rc) return rc;
+  std::copy(st.begin(), st.end(), host_flags);
+  return LBPC_OK;
+}
+
+int lbpc_get_state(lbpc_ctx* x, int32_t cavity, double* dev_f, double* dev_g) {
+  int rc = check_cavity(x, cavity);
+  if (rc) return rc;
+  if (!dev_g || (x->L.flow && !dev_f)) return fail(x, LBPC_EINVAL, "null output");
+  const CavParams* cp = x->d_params + cavity;
+  const int64_t n = x->L.ncell[cavity];
+  hipError_t e;
+  switch (x->L.prec) {
+    case 0: e = launch_get_state<0>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    case 1: e = launch_get_state<1>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    case 2: e = launch_get_state<2>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    default: e = launch_get_state<3>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+  }
+  HIPCHK(x, e);
+  return LBPC_OK;
+}
+
+int lbpc_set_state(lbpc_ctx* x, int32_t cavity, const double* dev_f, const double* dev_g) {
+  int rc = check_cavity(x, cavity);
+  if (rc) return rc;
+  if (!dev_g || (x->L.flow && !dev_f)) return fail(x, LBPC_EINVAL, "null input");
+  const CavParams* cp = x->d_params + cavity;
+  const int64_t n = x->L.ncell[cavity];
+  hipError_t e;
+  switch (x->L.prec) {
+    case 0: e = launch_set_state<0>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    case 1: e = launch_set_state<1>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    case 2: e = launch_set_state<2>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+    default: e = launch_set_state<3>(cp, n, x->L.flow, x->region[x->cur], dev_f, dev_g, x->stream); break;
+  }
+  HIPCHK(x, e);
+  x->adj.ready = false;
+  return LBPC_OK;
+}
+
+// Checkpoint: header, the current state region, budget records, status, wall fields.
+size_t lbpc_state_bytes(const lbpc_ctx* x) {
+  if (!x) return 0;
+  return 64 + static_cast<size_t>(x->L.region_bytes) + sizeof(BudgetRec) * x->L.batch +
+         sizeof(int32_t) * x->L.batch + sizeof(double) * x->L.tw_doubles;
+}
+
+int lbpc_save(lbpc_ctx* x, void* host_buf, size_t bytes) {
+  if (!x || !host_buf) return fail(x, LBPC_EINVAL, "null argument");
+  if (bytes < lbpc_state_bytes(x)) return fail(x, LBPC_ENOSPACE, "buffer too small");
+  int rc = flush(x);
+  if (rc) return rc;
+  char* p = static_cast<char*>(host_buf);
+  int64_t hdr[8] = {0x6c627063, x->L.batch, x->L.region_bytes, x->steps, x->L.prec, x->L.flow,
+                    x->L.tw_doubles, 0};
+  std::memcpy(p, hdr, sizeof(hdr));
+  p += 64;
+  HIPCHK(x, hipMemcpyAsync(p, x->region[x->cur], x->L.region_bytes, hipMemcpyDeviceToHost, x->stream));
+  p += x->L.region_bytes;
+  HIPCHK(x, hipMemcpyAsync(p, x->d_rec, sizeof(BudgetRec) * x->L.batch, hipMemcpyDeviceToHost, x->stream));
+  p += sizeof(BudgetRec) * x->L.batch;
+  HIPCHK(x, hipMemcpyAsync(p, x->d_status, sizeof(int32_t) * x->L.batch, hipMemcpyDeviceToHost, x->stream));
+  p += sizeof(int32_t) * x->L.batch;
+  HIPCHK(x, hipMemcpyAsync(p, x->d_tw, sizeof(double) * x->L.tw_doubles, hipMemcpyDeviceToHost, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  return LBPC_OK;
+}
+
+int lbpc_load(lbpc_ctx* x, const void* host_buf, size_t bytes) {
+  if (!x || !host_buf) return fail(x, LBPC_EINVAL, "null argument");
+  if (bytes < lbpc_state_bytes(x)) return fail(x, LBPC_ENOSPACE, "buffer too small");
+  const char* p = static_cast<const char*>(host_buf);
+  int64_t hdr[8];
+  std::memcpy(hdr, p, sizeof(hdr));
+  if (hdr[0] != 0x6c627063 || hdr[1] != x->L.batch || hdr[2] != x->L.region_bytes ||
+      hdr[4] != x->L.prec || hdr[5] != x->L.flow || hdr[6] != x->L.tw_doubles)
+    return fail(x, LBPC_EINVAL, "checkpoint does not match this context");
+  int rc = flush(x);
+  if (rc) return rc;
+  p += 64;
+  HIPCHK(x, hipMemcpyAsync(x->region[x->cur], p, x->L.region_bytes, hipMemcpyHostToDevice, x->stream));
+  p += x->L.region_bytes;
+  HIPCHK(x, hipMemcpyAsync(x->d_rec, p, sizeof(BudgetRec) * x->L.batch, hipMemcpyHostToDevice, x->stream));
+  p += sizeof(BudgetRec) * x->L.batch;
+  HIPCHK(x, hipMemcpyAsync(x->d_status, p, sizeof(int32_t) * x->L.batch, hipMemcpyHostToDevice, x->stream));
+  p += sizeof(int32_t) * x->L.batch;
+  HIPCHK(x, hipMemcpyAsync(x->d_tw, p, sizeof(double) * x->L.tw_doubles, hipMemcpyHostToDevice, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  x->steps = hdr[3];
+  x->unstable = false;
+  x->adj.ready = false;
+  std::vector<int32_t> st;
+  return read_status(x, st);
+}
+
+int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t graph_steps) {
+  if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
+  if (block < kMinTile || block > kMaxTile || block % 64)
+    return fail(x, LBPC_EINVAL, "block must be 64, 128, 192 or 256");
+  if (grid_blocks < 0) return fail(x, LBPC_EINVAL, "grid_blocks must be >= 0");
+  if (graph_steps < 0 || graph_steps > kRing || graph_steps % 2)
+    return fail(x, LBPC_EINVAL, "graph_steps must be even and <= 16");
+  int rc = flush(x);
+  if (rc) return rc;
+  x->grid = grid_blocks;
+  x->graph_steps = graph_steps;
+  if (block != x->block) {
+    x->block = block;
+    rc = build_tiles(x);
+    if (rc) return rc;
+  }
+  drop_graphs(x);
+  return LBPC_OK;
+}
+
+int lbpc_get_launch(const lbpc_ctx* x, int32_t* block, int32_t* grid_blocks, int32_t* graph_steps) {
+  if (!x) return LBPC_EINVAL;
+  if (block) *block = x->block;
+  if (grid_blocks) *grid_blocks = x->grid;
+  if (graph_steps) *graph_steps = x->graph_steps;
+  return LBPC_OK;
+}
+
+int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
+  if (!x || nsteps < 1) return fail(x, LBPC_EINVAL, "bad argument");
+  int rc = flush(x);
+  if (rc) return rc;
+  std::vector<hipEvent_t> ev(2 * static_cast<size_t>(nsteps));
+  for (auto& e : ev) HIPCHK(x, hipEventCreate(&e));
+  for (int i = 0; i < nsteps; ++i) {
+    HIPCHK(x, hipEventRecord(ev[2 * i], x->stream));
+    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * NPART;
+    HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, x->stream));
+    HIPCHK(x, hipEventRecord(ev[2 * i + 1], x->stream));
+    x->cur ^= 1;
+    x->steps += 1;
+    if (++x->pending == kRing) {
+      rc = flush(x);
+      if (rc) return rc;
+    }
+  }
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  double total = 0.0;
+  for (int i = 0; i < nsteps; ++i) {
+    float ms = 0.f;
+    HIPCHK(x, hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]));
+    total += ms;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  if (host_ms_out) *host_ms_out = total / nsteps;
+  return LBPC_OK;
+}
+
+int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
+  if (!x || trial_steps < 1) return fail(x, LBPC_EINVAL, "bad argument");
+  int rc = flush(x);
+  if (rc) return rc;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIPCHK(x, hipGetDevice(&dev));
+  HIPCHK(x, hipGetDeviceProperties(&prop, dev));
+  const int cus = prop.multiProcessorCount;
+  const int blocks[3] = {64, 128, 256};
+  const int grids[4] = {0, 2 * cus, 4 * cus, 8 * cus};
+  hipEvent_t e0, e1;
+  HIPCHK(x, hipEventCreate(&e0));
+  HIPCHK(x, hipEventCreate(&e1));
+  double best = 1e30;
+  int best_b = x->block, best_g = x->grid;
+  for (int b : blocks) {
+    x->block = b;
+    rc = build_tiles(x);
+    if (rc) return rc;
+    for (int g : grids) {
+      if (g > 0 && g >= x->ntiles) continue;
+      x->grid = g;
+      // the state is not advanced: every trial reads the current region and
+      // overwrites the other one, which the next real step rewrites completely
+      HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, x->stream));
+      HIPCHK(x, hipEventRecord(e0, x->stream));
+      for (int i = 0; i < trial_steps; ++i)
+        HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, x->stream));
+      HIPCHK(x, hipEventRecord(e1, x->stream));
+      HIPCHK(x, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(x, hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / trial_steps;
+      if (per < best) {
+        best = per;
+        best_b = b;
+        best_g = g;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  x->block = best_b;
+  x->grid = best_g;
+  rc = build_tiles(x);
+  if (rc) return rc;
+  if (host_ms_out) *host_ms_out = best;
+  return LBPC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checkpointed discrete adjoint
+// ---------------------------------------------------------------------------
+static AdjointPlan plan_adjoint(const lbpc_ctx* x, int64_t nsteps, int32_t every) {
+  AdjointPlan a;
+  a.nsteps = nsteps;
+  a.every = every;
+  a.nsnap = static_cast<int>((nsteps + every - 1) / every);
+  const size_t rb = static_cast<size_t>(x->L.region_bytes);
+  const size_t rsz = x->L.prec == 0 ? 8 : 4;
+  a.lam_bytes = align_up(static_cast<size_t>(x->L.plane[0]) * ((x->L.flow ? 19 : 0) + 7) * rsz);
+  size_t o = 0;
+  a.o_snap = o; o += rb * static_cast<size_t>(a.nsnap);
+  a.o_seg = o; o += rb * static_cast<size_t>(std::max(every - 1, 0));
+  a.o_lam0 = o; o += a.lam_bytes;
+  a.o_lam1 = o; o += a.lam_bytes;
+  a.o_dtw = o; o = align_up(o + sizeof(double) * x->L.tw_doubles);
+  a.total = o;
+  return a;
+}
+
+size_t lbpc_adjoint_workspace_bytes(const lbpc_ctx* x, int64_t nsteps, int32_t every) {
+  if (!x || nsteps < 1 || every < 1) return 0;
+  return plan_adjoint(x, nsteps, every).total;
+}
+
+int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t loss,
+                         void* dev_adj_ws, size_t bytes, double* host_loss) {
+  if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
+  if (x->L.batch != 1) return fail(x, LBPC_EINVAL, "the adjoint needs a single-cavity context");
+  if (x->L.prec > 1) return fail(x, LBPC_EINVAL, "the adjoint needs FP64 or FP32 storage");
+  if (nsteps < 1 || every < 1 || (loss != 0 && loss != 1))
+    return fail(x, LBPC_EINVAL, "bad nsteps, ckpt_every or loss");
+  if (x->unstable) return fail(x, LBPC_EUNSTABLE, "a cavity was flagged unstable");
+  AdjointPlan a = plan_adjoint(x, nsteps, every);
+  if (!dev_adj_ws || reinterpret_cast<uintptr_t>(dev_adj_ws) % kAlign)
+    return fail(x, LBPC_EINVAL, "adjoint workspace must be non-null and 256-byte aligned");
+  if (bytes < a.total) return fail(x, LBPC_ENOSPACE, "adjoint workspace too small");
+  a.ws = static_cast<char*>(dev_adj_ws);
+  a.bytes = bytes;
+  a.loss = loss;
+  int rc = flush(x);
+  if (rc) return rc;
+  const size_t rb = static_cast<size_t>(x->L.region_bytes);
+  for (int64_t s = 0; s < nsteps; s += every) {
+    HIPCHK(x, hipMemcpyAsync(a.ws + a.o_snap + rb * static_cast<size_t>(s / every),
+                             x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
+    rc = run_steps(x, std::min<int64_t>(every, nsteps - s));
+    if (rc) return rc;
+  }
+  a.end_step = x->steps;
+  double b[5];
+  rc = lbpc_budgets(x, b);
+  if (rc) return rc;
+  if (x->unstable) return fail(x, LBPC_EUNSTABLE, "the forward run became unstable");
+  const double area = static_cast<double>(x->cfg[0].ny) * x->cfg[0].nz;
+  if (host_loss) *host_loss = loss == 0 ? b[2] : b[2] / area;
+  a.ready = true;
+  x->adj = a;
+  return LBPC_OK;
+}
+
+int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* dev_dL_dT0) {
+  if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
+  AdjointPlan& a = x->adj;
+  if (!a.ready || a.end_step != x->steps)
+    return fail(x, LBPC_EINVAL, "no matching lbpc_adjoint_forward for the current state");
+  int rc = flush(x);
+  if (rc) return rc;
+  const size_t rb = static_cast<size_t>(x->L.region_bytes);
+  const int64_t n = x->L.ncell[0];
+  const CavParams* cp = x->d_params;
+  char* lam[2] = {a.ws + a.o_lam0, a.ws + a.o_lam1};
+  double* dtw = reinterpret_cast<double*>(a.ws + a.o_dtw);
+  HIPCHK(x, fill_zero(dtw, sizeof(double) * x->L.tw_doubles, x->stream));
+  const double area = static_cast<double>(x->cfg[0].ny) * x->cfg[0].nz;
+  const double scale = a.loss == 0 ? seed : seed / area;
+  const int prec = x->L.prec, flow = x->L.flow;
+  HIPCHK(x, prec == 0 ? launch_adj_seed<0>(cp, n, flow, scale, x->region[x->cur], lam[0], x->stream)
+                      : launch_adj_seed<1>(cp, n, flow, scale, x->region[x->cur], lam[0], x->stream));
+  int li = 0;  // lam[li] holds the adjoint of the state at the current time
+  auto state_at = [&](int64_t t, int64_t t0) -> char* {
+    const int64_t seg = t0 / a.every;
+    if (t == t0) return a.ws + a.o_snap + rb * static_cast<size_t>(seg);
+    return a.ws + a.o_seg + rb * static_cast<size_t>(t - t0 - 1);
+  };
+  for (int seg = a.nsnap - 1; seg >= 0; --seg) {
+    const int64_t t0 = static_cast<int64_t>(seg) * a.every;
+    const int64_t t1 = std::min<int64_t>(t0 + a.every, a.nsteps);
+    // recompute the states t0+1 .. t1-1 of this segment from its snapshot
+    for (int64_t t = t0; t + 1 < t1; ++t)
+      HIPCHK(x, dispatch_step(x, state_at(t, t0), state_at(t + 1, t0), nullptr, x->stream));
+    for (int64_t t = t1 - 1; t >= t0; --t) {
+      AdjArgs g;
+      g.cavs = x->d_params;
+      g.tiles = x->d_tiles;
+      g.ntiles = x->ntiles;
+      g.state = state_at(t, t0);
+      g.lam_in = lam[li];
+      g.lam_out = lam[li ^ 1];
+      g.dTw = dtw;
+      g.block = x->block;
+      g.flow = flow;
+      g.mrt = x->L.mrt;
+      g.stream = x->stream;
+      HIPCHK(x, prec == 0 ? launch_adjoint<0>(g) : launch_adjoint<1>(g));
+      li ^= 1;
+    }
+  }
+  if (dev_dL_dTw)
+    HIPCHK(x, hipMemcpyAsync(dev_dL_dTw, dtw, sizeof(double) * x->L.tw_doubles,
+                             hipMemcpyDeviceToDevice, x->stream));
+  if (dev_dL_dT0)
+    HIPCHK(x, prec == 0 ? launch_adj_T0<0>(cp, n, flow, a.ws + a.o_snap, lam[li], dev_dL_dT0, x->stream)
+                        : launch_adj_T0<1>(cp, n, flow, a.ws + a.o_snap, lam[li], dev_dL_dT0, x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  return LBPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+"""GPU tests of the systems around the step: launch shapes and graphs,
+checkpoint/resume, failure flags, 16-bit storage, batching at full size and
+full-size sampled parity (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import absdiff, make_cavity, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _state_bytes(cav):
+    f, g = cav.state()
+    out = [g.cpu().numpy()]
+    if f is not None:
+        out.append(f.cpu().numpy())
+    return out
+
+
+def test_launch_shapes_and_graphs_are_bitwise_identical():
+    """Block sizes 64/128/256, persistent grids and graph vs eager stepping give
+    the same state bit for bit (each cell's update is independent of the launch
+    shape)."""
+    cfg = W.melting_cavity(20, 1e5, 0.02, 0.1, precision=W.FP32)
+    cfg.update(ny=13, nz=11)
+    walls = {0: W.hot_wall_field(13, 11)}
+    ref = None
+    for block, grid, gs in [(256, 0, 16), (64, 0, 0), (128, 37, 4), (256, 512, 0), (192, 0, 2)]:
+        cav = make_cavity(cfg, walls=walls)
+        cav.set_launch(block, grid, gs)
+        cav.step(53)
+        s = _state_bytes(cav)
+        if ref is None:
+            ref = s
+        else:
+            for a, b in zip(s, ref):
+                assert np.array_equal(a, b), (block, grid, gs)
+        cav.close()
+
+
+def test_autotune_does_not_advance_state():
+    cfg = W.melting_cavity(16, 1e5, 0.02, 0.1, precision=W.FP32)
+    a = make_cavity(cfg)
+    a.step(10)
+    b = make_cavity(cfg)
+    b.step(10)
+    b.autotune(3)
+    a.step(7)
+    b.step(7)
+    for x, y in zip(_state_bytes(a), _state_bytes(b)):
+        assert np.array_equal(x, y)
+
+
+def test_save_load_resume_bitwise():
+    """Checkpoint at step 40, run to 100; reload, run again: identical state and
+    budgets (resume is bit-exact)."""
+    cfg = W.melting_cavity(18, 1e5, 0.02, 0.1, precision=W.FP32)
+    cav = make_cavity(cfg, walls={0: W.hot_wall_field(18, 18)})
+    cav.step(40)
+    blob = cav.save()
+    cav.step(60)
+    s1, b1 = _state_bytes(cav), cav.budgets()
+    cav.load(blob)
+    assert cav.budgets()[0, 4] == 40
+    cav.step(60)
+    s2, b2 = _state_bytes(cav), cav.budgets()
+    for x, y in zip(s1, s2):
+        assert np.array_equal(x, y)
+    assert np.array_equal(b1, b2)
+
+
+def test_unstable_cavity_is_flagged_and_frozen():
+    """A NaN initial temperature in one cavity of a batch sets its status bit;
+    the other cavity keeps stepping and further lbpc_step calls report it."""
+    from paper_1703_02652_amd import Cavity, LbpcError
+    c1 = W.melting_cavity(12, 1e4, 1.0, 0.1, precision=W.FP32)
+    c2 = dict(c1)
+    T_bad = np.zeros((12, 12, 12))
+    T_bad[3, 4, 5] = np.nan
+    cav = Cavity([c1, c2], T0=[np.zeros((12, 12, 12)), T_bad], device="cuda")
+    cav.step(20)
+    st = cav.status()
+    assert st.tolist() == [0, 1]
+    with pytest.raises(LbpcError) as e:
+        cav.step(1)
+    assert e.value.code == -4
+    fl = cav.fields(0, names=("fl",))["fl"]
+    assert float(fl.sum()) > 0
+
+
+def test_invalid_arguments_raise():
+    from paper_1703_02652_amd import Cavity, LbpcError
+    cfg = W.melting_cavity(8, 1e4, 1.0, 0.1, precision=W.FP32)
+    cav = Cavity(cfg, device="cuda")
+    with pytest.raises(LbpcError):
+        cav.set_launch(100, 0, 16)
+    with pytest.raises(LbpcError):
+        cav.set_launch(256, 0, 3)
+    with pytest.raises(LbpcError):
+        cav.set_wall_T(2, np.zeros((8, 8)))   # adiabatic face
+    with pytest.raises(LbpcError):
+        cav.fields(cavity=1)
+    c16 = dict(cfg, precision=W.FP16S)
+    c16cav = Cavity(c16, device="cuda")
+    with pytest.raises(LbpcError):
+        c16cav.adjoint_forward(10, 5)
+
+
+@pytest.mark.parametrize("prec", [W.FP16S, W.BF16S])
+def test_sixteen_bit_storage_error_against_fp64_oracle(prec):
+    """Shifted 16-bit populations with FP32 collision, 32^3 cavity, 400 steps.
+    The error against the FP64 oracle is reported; bounds are loose sanity
+    limits (FP16: 10 mantissa bits, BF16: 7)."""
+    cfg64 = W.melting_cavity(32, 1e5, 0.02, 0.1, precision=W.FP64)
+    cav = make_cavity(dict(cfg64, precision=prec))
+    cav.step(400)
+    ref = oracle.run(cfg64, oracle.init_state(cfg64), 400)
+    fl = cav.fields(names=("T", "fl", "u"))
+    rf = oracle.fields(cfg64, ref)
+    eT, efl = absdiff(fl["T"], rf["T"]), absdiff(fl["fl"], rf["fl"])
+    eu = absdiff(fl["uz"], rf["uz"]) / max(np.abs(rf["uz"]).max(), 1e-30)
+    dmean = abs(float(fl["fl"].sum()) - rf["fl"].sum()) / rf["fl"].size
+    print(f"prec {prec}: max|dT| {eT:.2e} max|dfl| {efl:.2e} rel|duz| {eu:.2e} "
+          f"d(mean fl) {dmean:.2e}")
+    lim = 5e-3 if prec == W.FP16S else 5e-2
+    assert eT < lim and dmean < lim
+
+
+def test_batch_of_64_cavities_first_steps_match_oracle_samples():
+    """The 64-cavity batch (sizes 32..96, random Ra, Pr, Ste) in one launch:
+    every cavity is stepped, and three of them match the FP64 oracle run alone
+    after 20 FP32 steps (liquid fraction within 1e-5)."""
+    from paper_1703_02652_amd import Cavity
+    cfgs, draws = W.batch_cavities()
+    cav = Cavity(cfgs, device="cuda")
+    cav.autotune(3)
+    cav.step(20)
+    b = cav.budgets()
+    assert (b[:, 3] > 0).all()     # heat entered every cavity
+    for i in (0, 17, 63):
+        c64 = dict(cfgs[i], precision=W.FP64)
+        ref = oracle.run(c64, oracle.init_state(c64), 20)
+        fl = cav.fields(i, names=("fl",))["fl"]
+        assert absdiff(fl, oracle.fields(c64, ref)["fl"]) < 1e-5, i
+
+
+def test_cavity128_full_size_one_step_against_oracle():
+    """Full-size 128^3 FP32 workload in the launch shape the benchmark tunes:
+    after 300 steps, the oracle's FP64 step from the GPU state (decoded) agrees
+    with the GPU's next state to FP32 rounding, and mass is conserved."""
+    cfg = W.cavity_128(precision=W.FP32)
+    cav = make_cavity(cfg)
+    cav.autotune(3)
+    cav.step(300)
+    f, g = cav.state()
+    st = (f.cpu().numpy(), g.cpu().numpy())
+    cav.step(1)
+    f1, g1 = cav.state()
+    ref = oracle.run(dict(cfg, precision=W.FP64), st, 1)
+    ef, eg = absdiff(f1, ref[0]), absdiff(g1, ref[1])
+    print(f"128^3 one step: max|df| {ef:.2e}, max|dg| {eg:.2e}")
+    assert ef < 2e-6 and eg < 2e-5
+    b = cav.budgets()[0]
+    assert abs(b[1] / 128**3 - 1.0) < 1e-6
