@@ -145,10 +145,13 @@ int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
 /* Launch configuration.  block: threads (and cells) per tile, 64..256, a
  * multiple of 64; grid_blocks: 0 for one workgroup per tile, else a persistent
  * grid that strides over the tile queue; graph_steps: steps per captured HIP
- * graph (even, 0 disables graphs). */
-int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t graph_steps);
+ * graph (even, at most 16, 0 disables graphs); xcd_runs: 1 for plain tile
+ * order, k > 1 to split the tile queue into k contiguous runs, one per
+ * accelerator complex die (workgroup ids equal modulo k), 8 on MI355X. */
+int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t graph_steps,
+                    int32_t xcd_runs);
 int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
-                    int32_t* graph_steps);
+                    int32_t* graph_steps, int32_t* xcd_runs);
 
 /* Time every candidate launch configuration on the real state (the state is
  * not advanced) and keep the fastest.  host_ms_out (nullable) receives the

@@ -91,9 +91,9 @@ def lib():
     L.lbpc_state_bytes.restype = sz
     L.lbpc_save.argtypes = [vp, vp, sz]
     L.lbpc_load.argtypes = [vp, vp, sz]
-    L.lbpc_set_launch.argtypes = [vp, i32, i32, i32]
+    L.lbpc_set_launch.argtypes = [vp, i32, i32, i32, i32]
     L.lbpc_get_launch.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                  ctypes.POINTER(i32)]
+                                  ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.lbpc_autotune.argtypes = [vp, i32, dp]
     L.lbpc_time_step_kernel.argtypes = [vp, i32, dp]
     L.lbpc_adjoint_workspace_bytes.argtypes = [vp, i64, i32]

@@ -166,14 +166,14 @@ class Cavity:
         self._check(self._L.lbpc_load(self._ctx, buf, len(blob)))
 
     # ------------------------------------------------------ launch shapes
-    def set_launch(self, block=256, grid=0, graph_steps=16):
-        self._check(self._L.lbpc_set_launch(self._ctx, block, grid, graph_steps))
+    def set_launch(self, block=256, grid=0, graph_steps=16, xcd_runs=8):
+        self._check(self._L.lbpc_set_launch(self._ctx, block, grid, graph_steps, xcd_runs))
 
     def get_launch(self):
-        b, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        self._check(self._L.lbpc_get_launch(self._ctx, ctypes.byref(b), ctypes.byref(g),
-                                            ctypes.byref(s)))
-        return b.value, g.value, s.value
+        """(block, grid, graph_steps, xcd_runs)"""
+        v = [ctypes.c_int32() for _ in range(4)]
+        self._check(self._L.lbpc_get_launch(self._ctx, *[ctypes.byref(a) for a in v]))
+        return tuple(a.value for a in v)
 
     def autotune(self, trial_steps=10):
         ms = ctypes.c_double()

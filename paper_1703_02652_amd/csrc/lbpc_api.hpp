@@ -16,6 +16,7 @@ struct alignas(16) CavParams {
   int32_t nxy;
   int32_t bc[6];
   int32_t tile0, ntiles;        // this cavity's tiles in the tile queue
+  int32_t chunk0, nchunks;      // this cavity's reduction chunks (runs of tiles)
   int32_t has_override;         // any finite sigma_override entry
   uint64_t div_nx_m, div_nxy_m; // magic multipliers: q = (i * m) >> s
   uint32_t div_nx_s, div_nxy_s;
@@ -50,9 +51,11 @@ struct StepArgs {
   int ntiles;
   const char* src;              // state region read (pre-collision state at t)
   char* dst;                    // state region written (pre-collision state at t+1)
-  double* partials;             // NPART doubles per tile, or null (no budgets)
+  double* partials;             // NPART doubles per tile (unused when budget = 0)
   const int32_t* status;        // per-cavity freeze flags
+  int budget;                   // 0 none, 1 wall inflow only, 2 all partials
   int block, grid;              // grid = 0: one workgroup per tile
+  int xcd;                      // > 1: XCD-contiguous tile order (grid rounded up)
   int flow, mrt;
   hipStream_t stream;
 };
@@ -65,7 +68,7 @@ struct AdjArgs {
   const char* lam_in;           // adjoint of the state at t+1 (compute format)
   char* lam_out;                // adjoint of the state at t
   double* dTw;                  // wall-temperature gradient accumulators (per cavity block)
-  int block;
+  int block, xcd;
   int flow, mrt;
   hipStream_t stream;
 };
@@ -95,9 +98,5 @@ template <int P> hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int f
                                           const char* state0, const char* lam, double* out,
                                           hipStream_t st);
 
-hipError_t launch_reduce(const CavParams* cavs, int batch, const double* partials,
-                         int64_t slot_stride, int nslots, int mode, BudgetRec* rec,
-                         int32_t* status, hipStream_t st);
-hipError_t launch_fill(void* p, int64_t nbytes, hipStream_t st);
 
 }  // namespace lbpc

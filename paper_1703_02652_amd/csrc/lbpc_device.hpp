@@ -389,19 +389,69 @@ __device__ __forceinline__ void block_partials(double* v, double* out, double (*
   __syncthreads();
 }
 
+// Wall inflow only: one double per tile (the other partials are written as 0).
+// Tiles without a nonzero inflow skip the reduction.
+__device__ __forceinline__ void block_flux(double v, double* out, double (*red)[NPART]) {
+  if (!__syncthreads_or(v != 0.0)) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) out[k] = 0.0;
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) red[wave][0] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w][0];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) out[k] = 0.0;
+    out[3] = s;
+  }
+  __syncthreads();
+}
+
+// Tiles handled by this workgroup.  With xcd > 1 (a grid that is a multiple of
+// xcd), the workgroups that the dispatcher sends to one XCD (block ids equal
+// modulo xcd) walk one contiguous run of the tile queue, so that neighbouring
+// tiles, whose links cross into each other, share that XCD's L2.
+struct TileIter {
+  int t, end, stride;
+};
+__device__ __forceinline__ TileIter tile_iter(int ntiles, int xcd) {
+  TileIter it;
+  if (xcd <= 1) {
+    it.t = blockIdx.x;
+    it.end = ntiles;
+    it.stride = gridDim.x;
+    return it;
+  }
+  const int chunk = (ntiles + xcd - 1) / xcd;
+  const int x = blockIdx.x % xcd, k = blockIdx.x / xcd;
+  it.t = x * chunk + k;
+  it.end = min(x * chunk + chunk, ntiles);
+  it.stride = gridDim.x / xcd;
+  return it;
+}
+
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
-template <int P, bool FLOW, bool MRT, bool BUDGET>
+// BUDGET: 0 no partials (recomputation inside the adjoint), 1 wall inflow only,
+// 2 all partials (h, rho, f_l, wall inflow, bad cells).
+template <int P, bool FLOW, bool MRT, int BUDGET>
 __global__ void __launch_bounds__(256)
-k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int xcd,
        const char* __restrict__ src, char* __restrict__ dst, double* __restrict__ partials,
        const int32_t* __restrict__ status) {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
   using R = typename Fmt<P>::R;
   __shared__ double red[4][NPART];
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (TileIter it = tile_iter(ntiles, xcd); it.t < it.end; it.t += it.stride) {
+    const int t = it.t;
     const int2 tl = tiles[t];
     const CavParams& c = cavs[tl.x];
     const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
@@ -491,7 +541,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         acc[4] = bad ? 1.0 : 0.0;
       }
     }
-    if (BUDGET) block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
+    if (BUDGET == 2) block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
+    if (BUDGET == 1) block_flux(acc[3], partials + static_cast<int64_t>(t) * NPART, red);
   }
 }
 

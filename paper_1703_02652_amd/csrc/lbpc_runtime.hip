@@ -19,6 +19,8 @@ namespace {
 constexpr int kRing = 16;           // budget partial slots (steps between reductions)
 constexpr int kMinTile = 64;        // smallest tile: one wavefront
 constexpr int kMaxTile = 256;       // largest tile: __launch_bounds__ of the kernels
+constexpr int kChunk = 256;         // tiles per first-pass reduction workgroup
+constexpr int kXcd = 8;             // XCDs of an MI355X: runs of the XCD-contiguous order
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
@@ -28,46 +30,77 @@ thread_local std::string g_err;
 // ---------------------------------------------------------------------------
 // Kernels that do not depend on the storage format
 // ---------------------------------------------------------------------------
+// Budget reduction, pass 1: one workgroup per (chunk, slot) sums the tile
+// partials of a run of at most kChunk tiles of one cavity in a fixed order.
 __global__ void __launch_bounds__(256)
-k_reduce(const CavParams* __restrict__ cavs, const double* __restrict__ partials,
-         int64_t slot_stride, int nslots, int mode, BudgetRec* __restrict__ rec,
-         int32_t* __restrict__ status) {
+k_reduce_chunks(const int4* __restrict__ chunks, const double* __restrict__ partials,
+                int64_t slot_stride, double* __restrict__ csum, int64_t csum_stride) {
   __shared__ double sh[256][NPART];
+  const int4 ch = chunks[blockIdx.x];  // (cavity, first tile, end tile, -)
+  const double* p = partials + static_cast<int64_t>(blockIdx.y) * slot_stride;
+  double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = ch.y + static_cast<int>(threadIdx.x); t < ch.z; t += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) v[k] += p[static_cast<int64_t>(t) * NPART + k];
+  }
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] = v[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + w][k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART)
+    csum[static_cast<int64_t>(blockIdx.y) * csum_stride +
+         static_cast<int64_t>(blockIdx.x) * NPART + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Pass 2: one wavefront per cavity folds its chunk sums slot by slot, in slot
+// order.  mode 0 (steps): the wall inflow of every slot is accumulated and the
+// other sums are those of the last slot (the step that wrote full partials);
+// mode 1 (measure of the current state): sums go to the now_* fields.
+__global__ void __launch_bounds__(64)
+k_reduce_final(const CavParams* __restrict__ cavs, const double* __restrict__ csum,
+               int64_t csum_stride, int nslots, int mode, BudgetRec* __restrict__ rec,
+               int32_t* __restrict__ status) {
   const CavParams& c = cavs[blockIdx.x];
+  BudgetRec& r = rec[blockIdx.x];
+  double cum = r.flux_cum, bad = 0.0, last[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int s = 0; s < nslots; ++s) {
     double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const double* p = partials + static_cast<int64_t>(s) * slot_stride * NPART;
-    for (int t = threadIdx.x; t < c.ntiles; t += blockDim.x) {
+    for (int j = threadIdx.x; j < c.nchunks; j += 64) {
 #pragma unroll
-      for (int k = 0; k < NPART; ++k) v[k] += p[static_cast<int64_t>(c.tile0 + t) * NPART + k];
+      for (int k = 0; k < NPART; ++k)
+        v[k] += csum[static_cast<int64_t>(s) * csum_stride + static_cast<int64_t>(c.chunk0 + j) * NPART + k];
     }
 #pragma unroll
-    for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] = v[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (static_cast<int>(threadIdx.x) < w) {
-#pragma unroll
-        for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + w][k];
-      }
-      __syncthreads();
+    for (int k = 0; k < NPART; ++k) last[k] = wave_total(v[k]);
+    cum += last[3];
+    bad += last[4];
+  }
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      r.H = last[0];
+      r.mass = last[1];
+      r.fl = last[2];
+      r.flux_last = last[3];
+      r.flux_cum = cum;
+      r.steps += nslots;
+    } else {
+      r.now_H = last[0];
+      r.now_mass = last[1];
+      r.now_fl = last[2];
     }
-    if (threadIdx.x == 0) {
-      BudgetRec& r = rec[blockIdx.x];
-      if (mode == 0) {
-        r.H = sh[0][0];
-        r.mass = sh[0][1];
-        r.fl = sh[0][2];
-        r.flux_last = sh[0][3];
-        r.flux_cum += sh[0][3];
-        r.steps += 1.0;
-      } else {
-        r.now_H = sh[0][0];
-        r.now_mass = sh[0][1];
-        r.now_fl = sh[0][2];
-      }
-      if (sh[0][4] > 0.0 || !isfinite(sh[0][0]) || !isfinite(sh[0][1])) status[blockIdx.x] = 1;
-    }
-    __syncthreads();
+    if (bad > 0.0 || !isfinite(last[0]) || !isfinite(last[1]) || !isfinite(cum)) status[blockIdx.x] = 1;
   }
 }
 
@@ -84,9 +117,9 @@ struct Layout {
   int batch = 0, prec = 0, flow = 0, mrt = 0;
   std::vector<int64_t> ncell, off, plane, cell_off, tw_off;
   std::vector<std::array<int64_t, 6>> twface;
-  int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, tw_doubles = 0;
-  size_t o_params = 0, o_tiles = 0, o_tw = 0, o_status = 0, o_rec = 0, o_part = 0,
-         o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
+  int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, max_chunks = 0, tw_doubles = 0;
+  size_t o_params = 0, o_tiles = 0, o_chunks = 0, o_csum = 0, o_tw = 0, o_status = 0, o_rec = 0,
+         o_part = 0, o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
 };
 
 size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
@@ -162,7 +195,7 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.flow = cfgs[0].flow;
   L.mrt = cfgs[0].enth_model;
   const size_t pb = pop_bytes(L.prec), g0b = g0_bytes(L.prec);
-  int64_t off = 0, cells = 0, tiles = 0, tw = 0;
+  int64_t off = 0, cells = 0, tiles = 0, chunks = 0, tw = 0;
   for (int i = 0; i < batch; ++i) {
     const lbpc_config& c = cfgs[i];
     const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
@@ -175,7 +208,9 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
                          static_cast<size_t>(plane) * g0b;
     off += static_cast<int64_t>(align_up(bytes));
     cells += n;
-    tiles += (n + kMinTile - 1) / kMinTile;
+    const int64_t ct = (n + kMinTile - 1) / kMinTile;
+    tiles += ct;
+    chunks += (ct + kChunk - 1) / kChunk;
     std::array<int64_t, 6> tf;
     int64_t fo = 0;
     for (int f = 0; f < 6; ++f) {
@@ -189,10 +224,13 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.region_bytes = off;
   L.total_cells = cells;
   L.max_tiles = tiles;
+  L.max_chunks = chunks;
   L.tw_doubles = tw;
   size_t o = 0;
   L.o_params = o; o = align_up(o + sizeof(CavParams) * batch);
   L.o_tiles = o; o = align_up(o + sizeof(int2) * tiles);
+  L.o_chunks = o; o = align_up(o + sizeof(int4) * chunks);
+  L.o_csum = o; o = align_up(o + sizeof(double) * NPART * chunks * kRing);
   L.o_tw = o; o = align_up(o + sizeof(double) * tw);
   L.o_status = o; o = align_up(o + sizeof(int32_t) * batch);
   L.o_rec = o; o = align_up(o + sizeof(BudgetRec) * batch);
@@ -286,6 +324,8 @@ struct lbpc_ctx {
   char* ws = nullptr;
   CavParams* d_params = nullptr;
   int2* d_tiles = nullptr;
+  int4* d_chunks = nullptr;
+  double* d_csum = nullptr;
   double* d_tw = nullptr;
   int32_t* d_status = nullptr;
   BudgetRec* d_rec = nullptr;
@@ -293,8 +333,8 @@ struct lbpc_ctx {
   double* d_mpart = nullptr;
   char* region[2] = {nullptr, nullptr};
   int cur = 0;
-  int block = 256, grid = 0, graph_steps = 16;
-  int ntiles = 0;
+  int block = 256, grid = 0, graph_steps = 16, xcd = kXcd;
+  int ntiles = 0, nchunks = 0;
   int pending = 0;
   int64_t steps = 0;
   bool unstable = false;
@@ -319,7 +359,7 @@ int fail(lbpc_ctx* x, int code, const std::string& msg) {
       return fail((x), LBPC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials,
+hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials, int budget,
                          hipStream_t st) {
   StepArgs a;
   a.cavs = x->d_params;
@@ -329,8 +369,10 @@ hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partia
   a.dst = dst;
   a.partials = partials;
   a.status = x->d_status;
+  a.budget = budget;
   a.block = x->block;
   a.grid = x->grid;
+  a.xcd = x->xcd;
   a.flow = x->L.flow;
   a.mrt = x->L.mrt;
   a.stream = st;
@@ -361,8 +403,11 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
 }
 
 hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(x->L.batch), dim3(256), 0, st, x->d_params, partials,
-                     static_cast<int64_t>(x->L.max_tiles), nslots, mode, x->d_rec, x->d_status);
+  const int64_t csum_stride = x->L.max_chunks * NPART;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(x->nchunks, nslots), dim3(256), 0, st, x->d_chunks,
+                     partials, static_cast<int64_t>(x->L.max_tiles) * NPART, x->d_csum, csum_stride);
+  hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64), 0, st, x->d_params, x->d_csum,
+                     csum_stride, nslots, mode, x->d_rec, x->d_status);
   return hipGetLastError();
 }
 
@@ -378,14 +423,23 @@ void drop_graphs(lbpc_ctx* x) {
 // Tile queue for the current block size: tiles never straddle cavities.
 int build_tiles(lbpc_ctx* x) {
   std::vector<int2> tiles;
+  std::vector<int4> chunks;
   for (int i = 0; i < x->L.batch; ++i) {
     x->hp[i].tile0 = static_cast<int32_t>(tiles.size());
     const int64_t n = x->L.ncell[i];
     for (int64_t c0 = 0; c0 < n; c0 += x->block) tiles.push_back(make_int2(i, static_cast<int>(c0)));
     x->hp[i].ntiles = static_cast<int32_t>(tiles.size()) - x->hp[i].tile0;
+    x->hp[i].chunk0 = static_cast<int32_t>(chunks.size());
+    for (int t = 0; t < x->hp[i].ntiles; t += kChunk)
+      chunks.push_back(make_int4(i, x->hp[i].tile0 + t,
+                                 x->hp[i].tile0 + std::min(t + kChunk, x->hp[i].ntiles), 0));
+    x->hp[i].nchunks = static_cast<int32_t>(chunks.size()) - x->hp[i].chunk0;
   }
   x->ntiles = static_cast<int>(tiles.size());
+  x->nchunks = static_cast<int>(chunks.size());
   HIPCHK(x, hipMemcpyAsync(x->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                           hipMemcpyHostToDevice, x->stream));
+  HIPCHK(x, hipMemcpyAsync(x->d_chunks, chunks.data(), sizeof(int4) * chunks.size(),
                            hipMemcpyHostToDevice, x->stream));
   HIPCHK(x, hipMemcpyAsync(x->d_params, x->hp.data(), sizeof(CavParams) * x->hp.size(),
                            hipMemcpyHostToDevice, x->stream));
@@ -405,7 +459,7 @@ int flush(lbpc_ctx* x) {
 // One eager step: partials into the next ring slot, reduction when the ring fills.
 int eager_step(lbpc_ctx* x) {
   double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * NPART;
-  HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, x->stream));
+  HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, 2, x->stream));
   x->cur ^= 1;
   x->steps += 1;
   if (++x->pending == kRing) return flush(x);
@@ -419,7 +473,8 @@ int capture(lbpc_ctx* x, int from) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < x->graph_steps && e == hipSuccess; ++i) {
     double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_tiles * NPART;
-    e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, x->cap);
+    e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, i + 1 == x->graph_steps ? 2 : 1,
+                      x->cap);
     c ^= 1;
   }
   if (e == hipSuccess) e = reduce(x, x->d_part, x->graph_steps, 0, x->cap);
@@ -510,6 +565,8 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
   x->ws = static_cast<char*>(dev_workspace);
   x->d_params = reinterpret_cast<CavParams*>(x->ws + L.o_params);
   x->d_tiles = reinterpret_cast<int2*>(x->ws + L.o_tiles);
+  x->d_chunks = reinterpret_cast<int4*>(x->ws + L.o_chunks);
+  x->d_csum = reinterpret_cast<double*>(x->ws + L.o_csum);
   x->d_tw = reinterpret_cast<double*>(x->ws + L.o_tw);
   x->d_status = reinterpret_cast<int32_t*>(x->ws + L.o_status);
   x->d_rec = reinterpret_cast<BudgetRec*>(x->ws + L.o_rec);
@@ -721,17 +778,20 @@ int lbpc_load(lbpc_ctx* x, const void* host_buf, size_t bytes) {
   return read_status(x, st);
 }
 
-int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t graph_steps) {
+int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t graph_steps,
+                    int32_t xcd_runs) {
   if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
   if (block < kMinTile || block > kMaxTile || block % 64)
     return fail(x, LBPC_EINVAL, "block must be 64, 128, 192 or 256");
   if (grid_blocks < 0) return fail(x, LBPC_EINVAL, "grid_blocks must be >= 0");
   if (graph_steps < 0 || graph_steps > kRing || graph_steps % 2)
     return fail(x, LBPC_EINVAL, "graph_steps must be even and <= 16");
+  if (xcd_runs < 1 || xcd_runs > 64) return fail(x, LBPC_EINVAL, "xcd_runs must lie in [1, 64]");
   int rc = flush(x);
   if (rc) return rc;
   x->grid = grid_blocks;
   x->graph_steps = graph_steps;
+  x->xcd = xcd_runs;
   if (block != x->block) {
     x->block = block;
     rc = build_tiles(x);
@@ -741,11 +801,13 @@ int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t gra
   return LBPC_OK;
 }
 
-int lbpc_get_launch(const lbpc_ctx* x, int32_t* block, int32_t* grid_blocks, int32_t* graph_steps) {
+int lbpc_get_launch(const lbpc_ctx* x, int32_t* block, int32_t* grid_blocks, int32_t* graph_steps,
+                    int32_t* xcd_runs) {
   if (!x) return LBPC_EINVAL;
   if (block) *block = x->block;
   if (grid_blocks) *grid_blocks = x->grid;
   if (graph_steps) *graph_steps = x->graph_steps;
+  if (xcd_runs) *xcd_runs = x->xcd;
   return LBPC_OK;
 }
 
@@ -758,7 +820,7 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   for (int i = 0; i < nsteps; ++i) {
     HIPCHK(x, hipEventRecord(ev[2 * i], x->stream));
     double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * NPART;
-    HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, x->stream));
+    HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, 1, x->stream));
     HIPCHK(x, hipEventRecord(ev[2 * i + 1], x->stream));
     x->cur ^= 1;
     x->steps += 1;
@@ -790,24 +852,27 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   const int cus = prop.multiProcessorCount;
   const int blocks[3] = {64, 128, 256};
   const int grids[4] = {0, 2 * cus, 4 * cus, 8 * cus};
+  const int xcds[2] = {1, kXcd};
   hipEvent_t e0, e1;
   HIPCHK(x, hipEventCreate(&e0));
   HIPCHK(x, hipEventCreate(&e1));
   double best = 1e30;
-  int best_b = x->block, best_g = x->grid;
+  int best_b = x->block, best_g = x->grid, best_x = x->xcd;
   for (int b : blocks) {
     x->block = b;
     rc = build_tiles(x);
     if (rc) return rc;
-    for (int g : grids) {
+    for (int g : grids)
+    for (int xc : xcds) {
       if (g > 0 && g >= x->ntiles) continue;
       x->grid = g;
+      x->xcd = xc;
       // the state is not advanced: every trial reads the current region and
       // overwrites the other one, which the next real step rewrites completely
-      HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, x->stream));
+      HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, 1, x->stream));
       HIPCHK(x, hipEventRecord(e0, x->stream));
       for (int i = 0; i < trial_steps; ++i)
-        HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, x->stream));
+        HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, 1, x->stream));
       HIPCHK(x, hipEventRecord(e1, x->stream));
       HIPCHK(x, hipEventSynchronize(e1));
       float ms = 0.f;
@@ -817,6 +882,7 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
         best = per;
         best_b = b;
         best_g = g;
+        best_x = xc;
       }
     }
   }
@@ -824,6 +890,7 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   hipEventDestroy(e1);
   x->block = best_b;
   x->grid = best_g;
+  x->xcd = best_x;
   rc = build_tiles(x);
   if (rc) return rc;
   if (host_ms_out) *host_ms_out = best;
@@ -921,7 +988,7 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
     const int64_t t1 = std::min<int64_t>(t0 + a.every, a.nsteps);
     // recompute the states t0+1 .. t1-1 of this segment from its snapshot
     for (int64_t t = t0; t + 1 < t1; ++t)
-      HIPCHK(x, dispatch_step(x, state_at(t, t0), state_at(t + 1, t0), nullptr, x->stream));
+      HIPCHK(x, dispatch_step(x, state_at(t, t0), state_at(t + 1, t0), nullptr, 0, x->stream));
     for (int64_t t = t1 - 1; t >= t0; --t) {
       AdjArgs g;
       g.cavs = x->d_params;
@@ -932,6 +999,7 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
       g.lam_out = lam[li ^ 1];
       g.dTw = dtw;
       g.block = x->block;
+      g.xcd = x->xcd;
       g.flow = flow;
       g.mrt = x->L.mrt;
       g.stream = x->stream;

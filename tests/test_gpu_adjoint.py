@@ -127,7 +127,8 @@ def test_autograd_function_matches_adjoint():
     loss = LbpcLoss.apply(Tw, cav, 40, 10, 0)
     loss.backward()
     g1 = Tw.grad.detach().cpu().numpy().copy()
-    cav.load(blob)
+    cav.load(blob)                      # restores the state and the constant wall
+    cav.set_wall_T(0, Tw.detach())
     L2 = cav.adjoint_forward(40, 10)
     dtw, _ = cav.adjoint_backward(seed=2.5)
     assert float(loss) == pytest.approx(L2, rel=1e-14)

@@ -27,16 +27,17 @@ def test_launch_shapes_and_graphs_are_bitwise_identical():
     cfg.update(ny=13, nz=11)
     walls = {0: W.hot_wall_field(13, 11)}
     ref = None
-    for block, grid, gs in [(256, 0, 16), (64, 0, 0), (128, 37, 4), (256, 512, 0), (192, 0, 2)]:
+    for launch in [(256, 0, 16, 8), (64, 0, 0, 1), (128, 37, 4, 8), (256, 512, 0, 1),
+                   (192, 0, 2, 3), (64, 24, 16, 8)]:
         cav = make_cavity(cfg, walls=walls)
-        cav.set_launch(block, grid, gs)
+        cav.set_launch(*launch)
         cav.step(53)
         s = _state_bytes(cav)
         if ref is None:
             ref = s
         else:
             for a, b in zip(s, ref):
-                assert np.array_equal(a, b), (block, grid, gs)
+                assert np.array_equal(a, b), launch
         cav.close()
 
 
@@ -99,9 +100,12 @@ def test_invalid_arguments_raise():
     with pytest.raises(LbpcError):
         cav.set_launch(256, 0, 3)
     with pytest.raises(LbpcError):
-        cav.set_wall_T(2, np.zeros((8, 8)))   # adiabatic face
+        cav.set_launch(256, 0, 16, 0)
     with pytest.raises(LbpcError):
-        cav.fields(cavity=1)
+        cav.set_wall_T(2, np.zeros((8, 8)))   # adiabatic face
+    import ctypes
+    with pytest.raises(LbpcError):      # cavity index checked by the library
+        cav._check(cav._L.lbpc_fields(cav._ctx, 5, 4, ctypes.c_void_p(0)))
     c16 = dict(cfg, precision=W.FP16S)
     c16cav = Cavity(c16, device="cuda")
     with pytest.raises(LbpcError):
