@@ -27,6 +27,19 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {0: 416, 1: 208, 2: 108, 3: 108}   # populations read + written once
 
 
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_step_fp32_cavity128.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, rec["source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return rec["traffic_bytes_per_launch"] if sha == rec["source_sha256_prefix"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -138,7 +151,7 @@ def main():
     alg_bytes = BYTES_PER_CELL[W.FP32] * cells
     achieved = alg_bytes / (main_r["kernel_ms"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
                     kernel="k_step<fp32, flow, MRT, budgets>",
                     bytes_per_launch=alg_bytes, kernel_ms=round(main_r["kernel_ms"], 5))
     cav.close()

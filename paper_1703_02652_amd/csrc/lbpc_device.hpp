@@ -51,6 +51,15 @@ template <> __device__ __forceinline__ bf16 enc<bf16>(double v) {
   return bf16{static_cast<uint16_t>(u >> 16)};
 }
 
+// Streaming loads: each stored population is read exactly once per step, so
+// the loads carry the non-temporal hint (they need not stay in the caches).
+template <class S> __device__ __forceinline__ S ld_stream(const S* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <> __device__ __forceinline__ bf16 ld_stream<bf16>(const bf16* p) {
+  return bf16{__builtin_nontemporal_load(&p->b)};
+}
+
 template <int P> struct View {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
@@ -464,11 +473,11 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
       R g[7];
       if (FLOW) {
 #pragma unroll
-        for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
+        for (int a = 0; a < 19; ++a) d[a] = dec(ld_stream(in.f + a * pl + cell));
       }
-      g[0] = static_cast<R>(in.g0[cell]);
+      g[0] = static_cast<R>(ld_stream(in.g0 + cell));
 #pragma unroll
-      for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
+      for (int a = 1; a < 7; ++a) g[a] = dec(ld_stream(in.g + (a - 1) * pl + cell));
 
       if (status[tl.x]) {  // frozen cavity: keep the state as it is
         if (FLOW) {
