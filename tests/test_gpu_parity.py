@@ -190,3 +190,35 @@ def test_fixed_point_bitwise_in_shifted_storage():
         cav.step(64)
         f1, g1 = cav.state()
         assert bool((f1 == f0).all()) and bool((g1 == 0).all()), prec
+
+
+@pytest.mark.parametrize("case", ["a", "b"])
+def test_two_phase_solidification_fp64(case):
+    """Sec. 3.1.2 solidification on a 192 x 2 x 2 lattice (periodic y, z), cases
+    (a) equal and (b) different solid/liquid C_p and lambda, 6000 steps: the GPU
+    state equals the oracle's (per-cell C_p(f_l) and sigma_chi(f_l))."""
+    cps, cpl, lams, laml = (1.0, 1.0, 0.4, 0.4) if case == "a" else (1.0, 2.0, 0.6, 0.15)
+    cfg = W.base_config(192, 2, 2, flow=0, enth_model=W.MRT, precision=W.FP64,
+                        face_bc=[W.DIRICHLET, W.ADIABATIC] + [W.PERIODIC] * 4,
+                        face_T=[-1.0, 0, 0, 0, 0, 0], cp_s=cps, cp_l=cpl, lambda_s=lams,
+                        lambda_l=laml, latent=250.0, T_m=0.0)
+    T0 = np.full((2, 2, 192), 1.0)
+    cav = make_cavity(cfg, T0=T0)
+    cav.step(6000)
+    _, g = cav.state()
+    ref = oracle.run(cfg, oracle.init_state(cfg, T0), 6000)
+    print(f"solidification ({case}): rel g {rel(g, ref[1]):.2e}")
+    assert rel(g, ref[1]) < FP64_TOL
+
+
+@pytest.mark.parametrize("model", [W.SRT, W.MRT])
+@pytest.mark.parametrize("tau", [0.564, 6.9])
+def test_tau_sweep_melting_fp64(model, tau):
+    """Sec. 3.1.1 relaxation times far from 1 (SRT leaks, MRT does not): GPU
+    equals the oracle for both models."""
+    cfg = W.stefan_1d(model, n=96, width=2, chi=(tau - 0.5) * 0.25)
+    cav = make_cavity(cfg)
+    cav.step(1500)
+    _, g = cav.state()
+    ref = oracle.run(cfg, oracle.init_state(cfg), 1500)
+    assert rel(g, ref[1]) < FP64_TOL
