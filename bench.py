@@ -170,6 +170,16 @@ def main():
             cv.close()
             del cv
             torch.cuda.empty_cache()
+        for case in (1, 2, 3):
+            c = W.table2_case(case)
+            cv, r = run_cavity(c, xs, 20, label=f"table2 case {case}")
+            cv.step(200)
+            r["after_steps"] = int(cv.budgets()[0, 4])
+            r["nusselt_hot_wall"] = round(float(cv.nusselt()), 4)
+            r["mean_fl"] = round(float(cv.budgets()[0, 2]) / (c["nx"] * c["ny"] * c["nz"]), 6)
+            extras[f"table2_case{case}_fp32"] = r
+            cv.close()
+            del cv
         from paper_1703_02652_amd import Cavity
         bcfgs, _ = W.batch_cavities()
         bc = Cavity(bcfgs, device="cuda")

@@ -117,10 +117,12 @@ int lbpc_step(lbpc_ctx* ctx, int64_t nsteps);
  * u = f_l (sum f e + F_b / 2) / rho (zero without flow). */
 int lbpc_fields(lbpc_ctx* ctx, int32_t cavity, uint32_t mask, double* dev_out);
 
-/* Per cavity, 5 FP64 values: H = sum h, mass = sum rho, sum f_l (current
+/* Per cavity, 6 FP64 values: H = sum h, mass = sum rho, sum f_l (current
  * state), the enthalpy that entered through fixed-temperature walls since
- * creation, and the number of steps taken.  Deterministic summation order.
- * Synchronises the stream. */
+ * creation, the number of steps taken, and the enthalpy the next step lets in
+ * through the x- face if it has a fixed temperature (exact lattice flux of the
+ * anti-bounce-back links; the wall heat flux behind the Nusselt number of
+ * Eq. (65)).  Deterministic summation order.  Synchronises the stream. */
 int lbpc_budgets(lbpc_ctx* ctx, double* host_out);
 
 /* Per-cavity status bits (1 = non-finite or out-of-bound state seen; such a

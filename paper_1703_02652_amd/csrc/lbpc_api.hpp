@@ -40,7 +40,8 @@ struct alignas(16) BudgetRec {
   double flux_last, flux_cum;   // wall enthalpy inflow: last step, since creation
   double steps;                 // steps reduced so far
   double now_H, now_mass, now_fl;  // sums of the current state (measure pass)
-  double pad[3];
+  double now_flux0;             // inflow through the x- face in the next step
+  double pad[2];
 };
 
 constexpr int NPART = 5;        // per-tile partials: h, rho, f_l, wall flux, bad cells
@@ -78,7 +79,7 @@ template <int P> hipError_t launch_init(const CavParams* cavs, const int2* tiles
                                         int block, int flow, char* dst, const double* T0,
                                         hipStream_t st);
 template <int P> hipError_t launch_measure(const CavParams* cavs, const int2* tiles, int ntiles,
-                                           int block, int flow, const char* src,
+                                           int block, int flow, int mrt, const char* src,
                                            double* partials, hipStream_t st);
 // single-cavity launchers: cav is a device pointer into the parameter table
 template <int P> hipError_t launch_fields(const CavParams* cav, int64_t n, int flow,

@@ -584,11 +584,15 @@ k_init(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
   }
 }
 
-// Sums of the current state per tile: h, rho, f_l (flux 0, bad-cell count).
-template <int P, bool FLOW>
+// Sums of the current state per tile: h, rho, f_l, the enthalpy that the next
+// step lets in through the x- face when it is a fixed-temperature face (the
+// hot wall of the cavity workloads; each x = 0 cell recomputes its collision to
+// get the outgoing g*_2 and applies the anti-bounce-back rule), bad cells.
+template <int P, bool FLOW, bool MRT>
 __global__ void __launch_bounds__(256)
 k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
           const char* __restrict__ src, double* __restrict__ partials) {
+  using R = typename Fmt<P>::R;
   __shared__ double red[4][NPART];
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int2 tl = tiles[t];
@@ -598,18 +602,39 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     if (cell < c.n) {
       const View<P> in = view<P>(src, c, FLOW);
       const int64_t pl = c.plane;
-      double h = static_cast<double>(in.g0[cell]);
+      R d[19], g[7];
+      if (FLOW) {
 #pragma unroll
-      for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+        for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
+      }
+      g[0] = static_cast<R>(in.g0[cell]);
+#pragma unroll
+      for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
+      double s6 = 0.0;
+#pragma unroll
+      for (int a = 1; a < 7; ++a) s6 += static_cast<double>(g[a]);
+      const double h = static_cast<double>(g[0]) + s6;
       double T, fl;
       phase_rule(c, h, T, fl);
       double rho = 0.0;
+      FlowMacro<R> q;
       if (FLOW) {
-        rho = c.fshift;
         double dr = 0.0;
 #pragma unroll
-        for (int a = 0; a < 19; ++a) dr += static_cast<double>(dec(in.f[a * pl + cell]));
-        rho += dr;
+        for (int a = 0; a < 19; ++a) dr += static_cast<double>(d[a]);
+        rho = c.fshift + dr;
+        q = flow_macro<R>(c, d, static_cast<R>(T), static_cast<R>(fl));
+      }
+      const Site st = make_site(c, cell);
+      if (st.lx && c.bc[0] == BC_DIRICHLET) {
+        const R Tr = static_cast<R>(T), flr = static_cast<R>(fl);
+        const R cp = static_cast<R>(c.cp_s) + flr * static_cast<R>(c.cp_l - c.cp_s);
+        const R sig = sigma_chi<R>(c, flr);
+        const R ux = FLOW ? q.ux : R(0), uy = FLOW ? q.uy : R(0), uz = FLOW ? q.uz : R(0);
+        if (MRT) enth_collide_mrt<R>(c, g, static_cast<R>(s6), Tr, cp, ux, uy, uz, sig);
+        else enth_collide_srt<R>(c, g, static_cast<R>(s6), Tr, cp, ux, uy, uz, sig);
+        const double Tw = c.tw[c.twface[0] + face_node(c, st, 0)];
+        acc[3] = c.omega_T * c.cp_ref * Tw - 2.0 * static_cast<double>(g[2]);
       }
       acc[0] = h;
       acc[1] = rho;

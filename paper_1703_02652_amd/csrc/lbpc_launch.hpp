@@ -52,11 +52,13 @@ hipError_t launch_init(const CavParams* cavs, const int2* tiles, int ntiles, int
 
 template <int P>
 hipError_t launch_measure(const CavParams* cavs, const int2* tiles, int ntiles, int block,
-                          int flow, const char* src, double* partials, hipStream_t st) {
-  if (flow)
-    hipLaunchKernelGGL((k_measure<P, true>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, src, partials);
-  else
-    hipLaunchKernelGGL((k_measure<P, false>), dim3(ntiles), dim3(block), 0, st, cavs, tiles, ntiles, src, partials);
+                          int flow, int mrt, const char* src, double* partials, hipStream_t st) {
+#define LBPC_MEAS(FL, MR)                                                                     \
+  hipLaunchKernelGGL((k_measure<P, FL, MR>), dim3(ntiles), dim3(block), 0, st, cavs, tiles,   \
+                     ntiles, src, partials)
+  if (flow) { if (mrt) LBPC_MEAS(true, true); else LBPC_MEAS(true, false); }
+  else { if (mrt) LBPC_MEAS(false, true); else LBPC_MEAS(false, false); }
+#undef LBPC_MEAS
   return hipGetLastError();
 }
 
@@ -116,7 +118,7 @@ hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int flow, const char* 
   template hipError_t launch_step<P>(const StepArgs&);                                            \
   template hipError_t launch_init<P>(const CavParams*, const int2*, int, int, int, char*,         \
                                      const double*, hipStream_t);                                 \
-  template hipError_t launch_measure<P>(const CavParams*, const int2*, int, int, int,             \
+  template hipError_t launch_measure<P>(const CavParams*, const int2*, int, int, int, int,        \
                                         const char*, double*, hipStream_t);                       \
   template hipError_t launch_fields<P>(const CavParams*, int64_t, int, const char*, uint32_t,     \
                                        double*, hipStream_t);                                     \

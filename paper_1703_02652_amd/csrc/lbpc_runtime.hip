@@ -99,6 +99,7 @@ k_reduce_final(const CavParams* __restrict__ cavs, const double* __restrict__ cs
       r.now_H = last[0];
       r.now_mass = last[1];
       r.now_fl = last[2];
+      r.now_flux0 = last[3];
     }
     if (bad > 0.0 || !isfinite(last[0]) || !isfinite(last[1]) || !isfinite(cum)) status[blockIdx.x] = 1;
   }
@@ -386,10 +387,10 @@ hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partia
 
 hipError_t dispatch_measure(lbpc_ctx* x, const char* src, double* partials) {
   switch (x->L.prec) {
-    case 0: return launch_measure<0>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
-    case 1: return launch_measure<1>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
-    case 2: return launch_measure<2>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
-    default: return launch_measure<3>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, src, partials, x->stream);
+    case 0: return launch_measure<0>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, x->L.mrt, src, partials, x->stream);
+    case 1: return launch_measure<1>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, x->L.mrt, src, partials, x->stream);
+    case 2: return launch_measure<2>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, x->L.mrt, src, partials, x->stream);
+    default: return launch_measure<3>(x->d_params, x->d_tiles, x->ntiles, x->block, x->L.flow, x->L.mrt, src, partials, x->stream);
   }
 }
 
@@ -667,11 +668,12 @@ int lbpc_budgets(lbpc_ctx* x, double* host_out) {
                            hipMemcpyDeviceToHost, x->stream));
   HIPCHK(x, hipStreamSynchronize(x->stream));
   for (int i = 0; i < x->L.batch; ++i) {
-    host_out[5 * i + 0] = rec[i].now_H;
-    host_out[5 * i + 1] = rec[i].now_mass;
-    host_out[5 * i + 2] = rec[i].now_fl;
-    host_out[5 * i + 3] = rec[i].flux_cum;
-    host_out[5 * i + 4] = static_cast<double>(x->steps);
+    host_out[6 * i + 0] = rec[i].now_H;
+    host_out[6 * i + 1] = rec[i].now_mass;
+    host_out[6 * i + 2] = rec[i].now_fl;
+    host_out[6 * i + 3] = rec[i].flux_cum;
+    host_out[6 * i + 4] = static_cast<double>(x->steps);
+    host_out[6 * i + 5] = rec[i].now_flux0;
   }
   std::vector<int32_t> st;
   return read_status(x, st);
@@ -948,7 +950,7 @@ int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t los
     if (rc) return rc;
   }
   a.end_step = x->steps;
-  double b[5];
+  double b[6];
   rc = lbpc_budgets(x, b);
   if (rc) return rc;
   if (x->unstable) return fail(x, LBPC_EUNSTABLE, "the forward run became unstable");

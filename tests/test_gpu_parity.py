@@ -222,3 +222,33 @@ def test_tau_sweep_melting_fp64(model, tau):
     _, g = cav.state()
     ref = oracle.run(cfg, oracle.init_state(cfg), 1500)
     assert rel(g, ref[1]) < FP64_TOL
+
+
+def test_hot_wall_flux_matches_oracle_inflow():
+    """The x- face inflow reported for the current state equals the oracle's
+    wall inflow of the next step when x- is the only fixed-temperature face."""
+    cfg = W.melting_cavity(14, 1e5, 0.1, 0.2, precision=W.FP64)
+    cfg["face_bc"] = [W.DIRICHLET] + [W.ADIABATIC] * 5
+    walls = {0: W.hot_wall_field(14, 14)}
+    tw = W.wall_fields(cfg, walls)
+    cav = make_cavity(cfg, walls=walls)
+    cav.step(37)
+    q = cav.budgets()[0, 5]
+    st = oracle.run(cfg, oracle.init_state(cfg), 37, tw=tw)
+    _, hist = oracle.run(cfg, st, 1, tw=tw, history=True)
+    assert q == pytest.approx(hist[0, 3], rel=1e-12)
+
+
+def test_conduction_nusselt_is_one():
+    """Eq. (65) on pure conduction between a hot and a cold wall (no buoyancy, all
+    liquid): at steady state the lattice wall flux gives Nu = 1."""
+    cfg = W.base_config(16, 4, 4, flow=1, precision=W.FP64, g_beta=0.0, T_m=-1.0,
+                        latent=1.0, lambda_s=0.1, lambda_l=0.1, nu=0.1,
+                        face_bc=[W.DIRICHLET, W.DIRICHLET] + [W.PERIODIC] * 4,
+                        face_T=[1.0, 0.0, 0, 0, 0, 0])
+    T0 = np.full((4, 4, 16), 0.5)
+    cav = make_cavity(cfg, T0=T0)
+    cav.step(20000)
+    nu = cav.nusselt()
+    print("conduction Nu", nu)
+    assert nu == pytest.approx(1.0, abs=1e-9)

@@ -124,6 +124,20 @@ def adjoint_cavity(n=96, precision=FP64):
     return melting_cavity(n, 1e4, 1.0, 0.1, precision=precision)
 
 
+# Sec. 3.3, Table 2: grid (x, y, z), Pr, Ra; Ste = 0.4 for all three cases.
+TABLE2 = {1: ((160, 160, 80), 0.02, 2.5e4), 2: ((160, 160, 80), 10.0, 2.5e4),
+          3: ((200, 200, 80), 10.0, 1.0e6)}
+
+
+def table2_case(case, precision=FP32, Ma=0.1):
+    """The paper's 3D melting cases on their printed grids (x hot-to-cold), with
+    l_c = nx for the lattice mapping; otherwise as melting_cavity."""
+    (nx, ny, nz), Pr, Ra = TABLE2[case]
+    cfg = melting_cavity(nx, Ra, Pr, 0.4, precision=precision, Ma=Ma)
+    cfg.update(ny=ny, nz=nz)
+    return cfg
+
+
 def hot_wall_field(ny, nz, seed=1703, amp=0.05):
     """Hot-wall temperature field T_w(y, z) = 1 + U(-amp, amp); layout [z][y]."""
     rng = np.random.default_rng(seed)
