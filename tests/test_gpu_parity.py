@@ -208,7 +208,10 @@ def test_two_phase_solidification_fp64(case):
     _, g = cav.state()
     ref = oracle.run(cfg, oracle.init_state(cfg, T0), 6000)
     print(f"solidification ({case}): rel g {rel(g, ref[1]):.2e}")
-    assert rel(g, ref[1]) < FP64_TOL
+    # long run with L = 250: mushy-zone enthalpy has no restoring force, so two
+    # FP64 rounding paths drift apart linearly (tests/test_oracle_conditioning.py)
+    from test_oracle_conditioning import DRIFT_PER_1000
+    assert rel(g, ref[1]) < DRIFT_PER_1000 * 6
 
 
 @pytest.mark.parametrize("model", [W.SRT, W.MRT])
@@ -241,8 +244,9 @@ def test_hot_wall_flux_matches_oracle_inflow():
 
 def test_conduction_nusselt_is_one():
     """Eq. (65) on pure conduction between a hot and a cold wall (no buoyancy, all
-    liquid): at steady state the lattice wall flux gives Nu = 1."""
-    cfg = W.base_config(16, 4, 4, flow=1, precision=W.FP64, g_beta=0.0, T_m=-1.0,
+    liquid, cold wall at T_m so that Delta T = T_h - T_m is the wall-to-wall
+    difference): at steady state the lattice wall flux gives Nu = 1."""
+    cfg = W.base_config(16, 4, 4, flow=1, precision=W.FP64, g_beta=0.0, T_m=0.0,
                         latent=1.0, lambda_s=0.1, lambda_l=0.1, nu=0.1,
                         face_bc=[W.DIRICHLET, W.DIRICHLET] + [W.PERIODIC] * 4,
                         face_T=[1.0, 0.0, 0, 0, 0, 0])
