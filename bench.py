@@ -73,6 +73,40 @@ def run_cavity(cfg, steps, warmup, launch=None, label=""):
                      launch=list(cav.get_launch()), unstable=int(st.max()))
 
 
+def precision_errors(n=256, steps=1000):
+    """Shifted FP16 / BF16 storage against the FP32 GPU run of the same cavity
+    (Ra 1e6, Pr 0.02 and 6.2): max and RMS errors of T, |u| and f_l, and the
+    difference of the mean liquid fraction."""
+    import torch
+    import workloads as W
+    from paper_1703_02652_amd import Cavity
+    out = {}
+    for Pr in (0.02, 6.2):
+        ref = None
+        for name, prec in (("fp32", W.FP32), ("fp16s", W.FP16S), ("bf16s", W.BF16S)):
+            cav = Cavity(W.precision_cavity(n, Pr, precision=prec), device="cuda")
+            cav.step(steps)
+            f = cav.fields(names=("T", "fl", "u"))
+            umag = torch.sqrt(f["ux"] ** 2 + f["uy"] ** 2 + f["uz"] ** 2)
+            cur = dict(T=f["T"], fl=f["fl"], u=umag)
+            if ref is None:
+                ref = cur
+            else:
+                e = {}
+                for k in ("T", "fl", "u"):
+                    d = (cur[k] - ref[k]).abs()
+                    e[f"max_{k}"] = float(d.max())
+                    e[f"rms_{k}"] = float(torch.sqrt((d * d).mean()))
+                e["d_mean_fl"] = float((cur["fl"].mean() - ref["fl"].mean()).abs())
+                e["max_u_ref"] = float(ref["u"].max())
+                out[f"Pr{Pr}_{name}_vs_fp32"] = e
+            cav.close()
+            del cav
+            torch.cuda.empty_cache()
+        del ref
+    return dict(cells=n**3, steps=steps, errors=out)
+
+
 def cpu_baseline(cfg, target_s=10.0, max_steps=40):
     """The FP64 CPU oracle on the same workload, a bounded number of steps."""
     import oracle
@@ -194,6 +228,8 @@ def main():
         bc.close()
         del bc
         torch.cuda.empty_cache()
+        extras["precision256_errors"] = precision_errors()
+        log(f"[bench] precision errors: {extras['precision256_errors']}")
         extras["adjoint96_fp32"] = adjoint_ratio(W.FP32)
         log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
         extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)

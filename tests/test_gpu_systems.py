@@ -168,3 +168,25 @@ def test_cavity128_full_size_one_step_against_oracle():
     assert ef < 2e-6 and eg < 2e-5
     b = cav.budgets()[0]
     assert abs(b[1] / 128**3 - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("Pr", [0.02, 6.2])
+def test_sixteen_bit_errors_at_64_against_fp64_oracle(Pr):
+    """Precision workload shape (Ra 1e6) at 64^3, 300 steps: FP32, FP16 and BF16
+    storage against the FP64 oracle; errors are reported (printed) and bounded
+    loosely; FP32 keeps the liquid fraction within 1e-5."""
+    cfg64 = W.precision_cavity(64, Pr, precision=W.FP64)
+    ref = oracle.run(cfg64, oracle.init_state(cfg64), 300)
+    rf = oracle.fields(cfg64, ref)
+    umag_ref = np.sqrt(rf["ux"] ** 2 + rf["uy"] ** 2 + rf["uz"] ** 2)
+    for prec, lim in ((W.FP32, 1e-5), (W.FP16S, 5e-3), (W.BF16S, 5e-2)):
+        cav = make_cavity(dict(cfg64, precision=prec))
+        cav.step(300)
+        fl = cav.fields(names=("T", "fl", "u"))
+        umag = np.sqrt(sum(fl[k].cpu().numpy() ** 2 for k in ("ux", "uy", "uz")))
+        eT, efl = absdiff(fl["T"], rf["T"]), absdiff(fl["fl"], rf["fl"])
+        eu = np.abs(umag - umag_ref).max()
+        print(f"Pr {Pr} prec {prec}: max|dT| {eT:.2e} max|dfl| {efl:.2e} max|d|u|| {eu:.2e} "
+              f"(max|u| {umag_ref.max():.2e})")
+        assert efl < lim and eT < 10 * lim
+        cav.close()
