@@ -53,8 +53,9 @@ enum {
 };
 
 /* Population storage.  The shifted formats store f_a - w_a rho0 (the deviation
- * from rest); g_0 is kept in FP32 in the 16-bit formats; collision arithmetic
- * is FP32 for every format but FP64. */
+ * from rest); g_0, which carries the latent heat, is FP64 in every format and
+ * the enthalpy -> (T, f_l) update is FP64; collision arithmetic is FP32 for
+ * every format but FP64. */
 enum { LBPC_FP64 = 0, LBPC_FP32 = 1, LBPC_FP16S = 2, LBPC_BF16S = 3 };
 enum { LBPC_SRT = 0, LBPC_MRT = 1 };
 
@@ -155,8 +156,10 @@ int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t g
 int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
                     int32_t* graph_steps, int32_t* xcd_runs);
 
-/* Time every candidate launch configuration on the real state (the state is
- * not advanced) and keep the fastest.  host_ms_out (nullable) receives the
+/* Time every candidate launch configuration (tile size, persistent grid, XCD
+ * order) with real alternating steps from the current state and keep the
+ * fastest.  The state is copied to host memory first and restored afterwards,
+ * so tuning does not advance the run.  host_ms_out (nullable) receives the
  * best average step-kernel time in milliseconds.  Synchronises the stream. */
 int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 

@@ -197,13 +197,14 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
 #pragma unroll
       for (int a = 0; a < 19; ++a) d[a] = dec(st.f[a * pl + cell]);
     }
-    g[0] = static_cast<R>(st.g0[cell]);
+    const double g0d = st.g0[cell];
+    g[0] = static_cast<R>(g0d);
 #pragma unroll
     for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
     double s6d = 0.0;
 #pragma unroll
     for (int a = 1; a < 7; ++a) s6d += static_cast<double>(g[a]);
-    const double hd = static_cast<double>(g[0]) + s6d;
+    const double hd = g0d + s6d;
     double Td, fld;
     phase_rule(c, hd, Td, fld);
     // slopes of the phase rule on the branch taken

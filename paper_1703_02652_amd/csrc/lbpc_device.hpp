@@ -5,7 +5,7 @@
 // Layout: every cavity owns, inside a state region, 19 f planes, 6 planes for
 // g_1..g_6 and one plane for g_0, each plane `plane` elements long, cell index
 // x + nx (y + ny z).  FP64 stores the populations as they are; the other
-// formats store f_a - w_a rho0 (deviation from rest), g_0 in FP32.
+// formats store f_a - w_a rho0 (deviation from rest); g_0 is FP64 everywhere.
 //
 // Step scheme: one thread per cell reads its own pre-collision populations
 // (aligned, coalesced), does both collisions in registers and pushes every
@@ -28,10 +28,13 @@ struct bf16 {
 };
 
 template <int P> struct Fmt;
+// g_0 carries the latent heat (h = g_0 + sum of the small moving populations):
+// it is stored in FP64 in every format so that the small per-step enthalpy
+// changes of a mushy cell are not rounded away against its large value.
 template <> struct Fmt<P64> { using S = double;   using S0 = double; using R = double; };
-template <> struct Fmt<P32> { using S = float;    using S0 = float;  using R = float; };
-template <> struct Fmt<P16> { using S = _Float16; using S0 = float;  using R = float; };
-template <> struct Fmt<PB16> { using S = bf16;    using S0 = float;  using R = float; };
+template <> struct Fmt<P32> { using S = float;    using S0 = double; using R = float; };
+template <> struct Fmt<P16> { using S = _Float16; using S0 = double; using R = float; };
+template <> struct Fmt<PB16> { using S = bf16;    using S0 = double; using R = float; };
 
 __device__ __forceinline__ double dec(double v) { return v; }
 __device__ __forceinline__ float dec(float v) { return v; }
@@ -325,9 +328,10 @@ __device__ __forceinline__ void mrt_rates(const CavParams& c, R sig, R* r) {
 
 // D3Q7 MRT collision, Eq. (21)-(25).  n_4 - n_4^eq is formed as
 // -7 sum_{a>0} g_a + 21 omega_T C_p,ref T (the g_0 terms cancel exactly), which
-// keeps the latent-heat-sized g_0 out of the difference.
+// keeps the latent-heat-sized g_0 out of the difference.  g_1..g_6 are updated
+// in place; the change of g_0 is returned (the caller adds it in FP64).
 template <class R>
-__device__ __forceinline__ void enth_collide_mrt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
+__device__ __forceinline__ R enth_collide_mrt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
                                                  R uy, R uz, R sig) {
   R r[7];
   mrt_rates(c, sig, r);
@@ -340,7 +344,7 @@ __device__ __forceinline__ void enth_collide_mrt(const CavParams& c, R* g, R s6,
   const R g12 = g[1] + g[2], g34 = g[3] + g[4], g56 = g[5] + g[6];
   const R b5 = r[5] * (static_cast<R>(2) * g12 - (g34 + g56)) * static_cast<R>(1.0 / 12.0);
   const R b6 = r[6] * (g34 - g56) * static_cast<R>(0.25);
-  g[0] -= static_cast<R>(6) * b4;
+  const R dg0 = -static_cast<R>(6) * b4;
   const R ax = -b4 + static_cast<R>(2) * b5;
   const R ay = -b4 - b5 + b6;
   const R az = -b4 - b5 - b6;
@@ -350,22 +354,24 @@ __device__ __forceinline__ void enth_collide_mrt(const CavParams& c, R* g, R s6,
   g[4] -= ay - b2;
   g[5] -= az + b3;
   g[6] -= az - b3;
+  return dg0;
 }
 
 // D3Q7 SRT (BGK) collision, Eq. (5)-(8): g^eq_0 = h - 3 omega_T C_p,ref T,
 // g^eq_a = (omega_T / 2) C_p,ref T + (u.e_a / 2) C_p T.
 template <class R>
-__device__ __forceinline__ void enth_collide_srt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
-                                                 R uy, R uz, R inv_tau) {
+__device__ __forceinline__ R enth_collide_srt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
+                                              R uy, R uz, R inv_tau) {
   const R wT = static_cast<R>(0.5 * c.omega_T * c.cp_ref) * T;
   const R hq = static_cast<R>(0.5) * cp * T;
-  g[0] -= inv_tau * (static_cast<R>(3.0 * c.omega_T * c.cp_ref) * T - s6);
+  const R dg0 = -inv_tau * (static_cast<R>(3.0 * c.omega_T * c.cp_ref) * T - s6);
   g[1] -= inv_tau * (g[1] - (wT + hq * ux));
   g[2] -= inv_tau * (g[2] - (wT - hq * ux));
   g[3] -= inv_tau * (g[3] - (wT + hq * uy));
   g[4] -= inv_tau * (g[4] - (wT - hq * uy));
   g[5] -= inv_tau * (g[5] - (wT + hq * uz));
   g[6] -= inv_tau * (g[6] - (wT - hq * uz));
+  return dg0;
 }
 
 // ---------------------------------------------------------------------------
@@ -475,7 +481,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
 #pragma unroll
         for (int a = 0; a < 19; ++a) d[a] = dec(ld_stream(in.f + a * pl + cell));
       }
-      g[0] = static_cast<R>(ld_stream(in.g0 + cell));
+      const double g0d = ld_stream(in.g0 + cell);
+      g[0] = static_cast<R>(g0d);
 #pragma unroll
       for (int a = 1; a < 7; ++a) g[a] = dec(ld_stream(in.g + (a - 1) * pl + cell));
 
@@ -484,7 +491,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
 #pragma unroll
           for (int a = 0; a < 19; ++a) out.f[a * pl + cell] = enc<S>(d[a]);
         }
-        out.g0[cell] = static_cast<S0>(g[0]);
+        out.g0[cell] = g0d;
 #pragma unroll
         for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(g[a]);
       } else {
@@ -492,7 +499,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         double s6d = 0.0;
 #pragma unroll
         for (int a = 1; a < 7; ++a) s6d += static_cast<double>(g[a]);
-        const double hd = static_cast<double>(g[0]) + s6d;
+        const double hd = g0d + s6d;
         double Td, fld;
         phase_rule(c, hd, Td, fld);
         const R T = static_cast<R>(Td), fl = static_cast<R>(fld), s6 = static_cast<R>(s6d);
@@ -510,8 +517,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
           flow_collide<R>(c, d, q);
         }
         const R sig = sigma_chi<R>(c, fl);
-        if (MRT) enth_collide_mrt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
-        else enth_collide_srt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
+        const R dg0 = MRT ? enth_collide_mrt<R>(c, g, s6, T, cp, ux, uy, uz, sig)
+                          : enth_collide_srt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
 
         // stream: push every post-collision population along its link
         const Site s = make_site(c, cell);
@@ -525,7 +532,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
             else out.f[Q19OPP[a] * pl + cell] = enc<S>(d[a]);  // halfway bounce-back
           }
         }
-        out.g0[cell] = static_cast<S0>(g[0]);
+        out.g0[cell] = g0d + static_cast<double>(dg0);
         double flux = 0.0;
 #pragma unroll
         for (int a = 1; a < 7; ++a) {

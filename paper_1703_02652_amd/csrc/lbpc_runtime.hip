@@ -124,7 +124,7 @@ struct Layout {
 };
 
 size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
-size_t g0_bytes(int prec) { return prec == 0 ? 8 : 4; }
+size_t g0_bytes(int) { return 8; }  // g_0 is FP64 in every storage format
 
 int64_t face_size(const lbpc_config& c, int face) {
   const int d = face / 2;
@@ -855,11 +855,20 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   const int blocks[3] = {64, 128, 256};
   const int grids[4] = {0, 2 * cus, 4 * cus, 8 * cus};
   const int xcds[2] = {1, kXcd};
+  // Trials run real, alternating steps (the cache state of a run differs from
+  // re-reading one unchanged region); the state is saved to the host first and
+  // restored afterwards, so tuning leaves the run untouched.
+  std::vector<char> saved(static_cast<size_t>(x->L.region_bytes));
+  const int cur0 = x->cur;
+  HIPCHK(x, hipMemcpyAsync(saved.data(), x->region[cur0], saved.size(), hipMemcpyDeviceToHost,
+                           x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
   hipEvent_t e0, e1;
   HIPCHK(x, hipEventCreate(&e0));
   HIPCHK(x, hipEventCreate(&e1));
   double best = 1e30;
   int best_b = x->block, best_g = x->grid, best_x = x->xcd;
+  int c = cur0;
   for (int b : blocks) {
     x->block = b;
     rc = build_tiles(x);
@@ -869,12 +878,11 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
       if (g > 0 && g >= x->ntiles) continue;
       x->grid = g;
       x->xcd = xc;
-      // the state is not advanced: every trial reads the current region and
-      // overwrites the other one, which the next real step rewrites completely
-      HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, 1, x->stream));
+      for (int i = 0; i < 2; ++i, c ^= 1)
+        HIPCHK(x, dispatch_step(x, x->region[c], x->region[c ^ 1], x->d_part, 1, x->stream));
       HIPCHK(x, hipEventRecord(e0, x->stream));
-      for (int i = 0; i < trial_steps; ++i)
-        HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], x->d_part, 1, x->stream));
+      for (int i = 0; i < trial_steps; ++i, c ^= 1)
+        HIPCHK(x, dispatch_step(x, x->region[c], x->region[c ^ 1], x->d_part, 1, x->stream));
       HIPCHK(x, hipEventRecord(e1, x->stream));
       HIPCHK(x, hipEventSynchronize(e1));
       float ms = 0.f;
@@ -890,6 +898,10 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  HIPCHK(x, hipMemcpyAsync(x->region[cur0], saved.data(), saved.size(), hipMemcpyHostToDevice,
+                           x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  x->cur = cur0;
   x->block = best_b;
   x->grid = best_g;
   x->xcd = best_x;
