@@ -157,6 +157,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="cavity128_fp32",
+                    choices=["cavity128_fp32", "cavity256_fp32", "cavity256_fp16s", "cavity256_bf16s",
+                             "cavity128_fp64"],
+                    help="cavity timed for the main line (profiling of the other kernels)")
     ap.add_argument("--launch", default=None,
                     help="block,grid,graph_steps instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -179,14 +183,20 @@ def main():
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
 
-    cfg = W.cavity_128(precision=W.FP32)
+    prec = {"fp32": W.FP32, "fp16s": W.FP16S, "bf16s": W.BF16S, "fp64": W.FP64}[
+        args.workload.split("_")[1]]
+    if args.workload.startswith("cavity128"):
+        cfg = W.cavity_128(precision=prec)
+    else:
+        cfg = W.precision_cavity(256, 0.02, precision=prec)
     cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
-    cav, main_r = run_cavity(cfg, args.steps, args.warmup, launch=launch, label="cavity128 fp32")
-    alg_bytes = BYTES_PER_CELL[W.FP32] * cells
+    cav, main_r = run_cavity(cfg, args.steps, args.warmup, launch=launch, label=args.workload)
+    alg_bytes = BYTES_PER_CELL[prec] * cells
     achieved = alg_bytes / (main_r["kernel_ms"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                    kernel="k_step<fp32, flow, MRT, budgets>",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic() if args.workload == "cavity128_fp32" else None,
+                    kernel=f"k_step<{args.workload.split('_')[1]}, flow, MRT, wall-inflow partials>",
                     bytes_per_launch=alg_bytes, kernel_ms=round(main_r["kernel_ms"], 5))
     cav.close()
     del cav
@@ -237,16 +247,19 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(W.cavity_128(precision=W.FP64))
+        cpu = cpu_baseline(dict(cfg, precision=W.FP64))
         log(f"[bench] cpu baseline: {cpu}")
 
     out = dict(
-        metric="coupled flow+enthalpy MLUPS (128^3 cavity, FP32)",
+        metric=f"coupled flow+enthalpy MLUPS ({args.workload})",
         value=round(main_r["mlups"], 1), unit="MLUPS", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(main_r["ms_per_step"], 5), higher_is_better=True,
-        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="cavity128_Ra1e5_Pr0.02_Ste0.1", lattice="D3Q19 MRT + D3Q7 MRT",
-                    cells=cells, storage="fp32", launch=main_r["launch"]),
+        scaling="weak", vs_baseline=None, dtype="f64" if prec == W.FP64 else "f32",
+        data="synthetic",
+        config=dict(workload=("cavity128_Ra1e5_Pr0.02_Ste0.1" if args.workload.startswith("cavity128")
+                              else "cavity256_Ra1e6_Pr0.02_Ste0.1"),
+                    lattice="D3Q19 MRT + D3Q7 MRT", cells=cells,
+                    storage=args.workload.split("_")[1], launch=main_r["launch"]),
         roofline=roofline, cpu_baseline=cpu, extras=extras,
     )
     print(json.dumps(out), flush=True)

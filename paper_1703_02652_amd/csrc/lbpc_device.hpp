@@ -23,10 +23,6 @@ namespace lbpc {
 // ---------------------------------------------------------------------------
 // Storage formats
 // ---------------------------------------------------------------------------
-struct bf16 {
-  uint16_t b;
-};
-
 template <int P> struct Fmt;
 // g_0 carries the latent heat (h = g_0 + sum of the small moving populations):
 // it is stored in FP64 in every format so that the small per-step enthalpy
@@ -34,12 +30,12 @@ template <int P> struct Fmt;
 template <> struct Fmt<P64> { using S = double;   using S0 = double; using R = double; };
 template <> struct Fmt<P32> { using S = float;    using S0 = double; using R = float; };
 template <> struct Fmt<P16> { using S = _Float16; using S0 = double; using R = float; };
-template <> struct Fmt<PB16> { using S = bf16;    using S0 = double; using R = float; };
+template <> struct Fmt<PB16> { using S = __bf16;  using S0 = double; using R = float; };
 
 __device__ __forceinline__ double dec(double v) { return v; }
 __device__ __forceinline__ float dec(float v) { return v; }
 __device__ __forceinline__ float dec(_Float16 v) { return static_cast<float>(v); }
-__device__ __forceinline__ float dec(bf16 v) { return __uint_as_float(static_cast<uint32_t>(v.b) << 16); }
+__device__ __forceinline__ float dec(__bf16 v) { return static_cast<float>(v); }
 
 template <class S> __device__ __forceinline__ S enc(double v);
 template <> __device__ __forceinline__ double enc<double>(double v) { return v; }
@@ -47,11 +43,8 @@ template <> __device__ __forceinline__ float enc<float>(double v) { return stati
 template <> __device__ __forceinline__ _Float16 enc<_Float16>(double v) {
   return static_cast<_Float16>(static_cast<float>(v));
 }
-template <> __device__ __forceinline__ bf16 enc<bf16>(double v) {
-  // round to nearest even on the upper 16 bits of the FP32 pattern
-  uint32_t u = __float_as_uint(static_cast<float>(v));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return bf16{static_cast<uint16_t>(u >> 16)};
+template <> __device__ __forceinline__ __bf16 enc<__bf16>(double v) {
+  return static_cast<__bf16>(static_cast<float>(v));  // round to nearest even
 }
 
 // Streaming loads: each stored population is read exactly once per step, so
@@ -59,8 +52,9 @@ template <> __device__ __forceinline__ bf16 enc<bf16>(double v) {
 template <class S> __device__ __forceinline__ S ld_stream(const S* p) {
   return __builtin_nontemporal_load(p);
 }
-template <> __device__ __forceinline__ bf16 ld_stream<bf16>(const bf16* p) {
-  return bf16{__builtin_nontemporal_load(&p->b)};
+template <> __device__ __forceinline__ __bf16 ld_stream<__bf16>(const __bf16* p) {
+  const uint16_t b = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+  return __builtin_bit_cast(__bf16, b);
 }
 
 template <int P> struct View {
