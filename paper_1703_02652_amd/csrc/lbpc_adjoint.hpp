@@ -201,10 +201,8 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     g[0] = static_cast<R>(g0d);
 #pragma unroll
     for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
-    double s6d = 0.0;
-#pragma unroll
-    for (int a = 1; a < 7; ++a) s6d += static_cast<double>(g[a]);
-    const double hd = g0d + s6d;
+    const R s6 = moving_sum(g);
+    const double hd = g0d + static_cast<double>(s6);
     double Td, fld;
     phase_rule(c, hd, Td, fld);
     // slopes of the phase rule on the branch taken
@@ -212,7 +210,7 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     if (hd <= c.hs) { dT_dh = static_cast<R>(c.inv_cps); dfl_dh = 0; }
     else if (hd >= c.hl) { dT_dh = static_cast<R>(c.inv_cpl); dfl_dh = 0; }
     else { dT_dh = 0; dfl_dh = static_cast<R>(c.inv_dh); }
-    const R T = static_cast<R>(Td), fl = static_cast<R>(fld), s6 = static_cast<R>(s6d);
+    const R T = static_cast<R>(Td), fl = static_cast<R>(fld);
     const R cp = static_cast<R>(c.cp_s) + fl * static_cast<R>(c.cp_l - c.cp_s);
     FlowMacro<R> q;
     if (FLOW) q = flow_macro<R>(c, d, T, fl);
@@ -378,9 +376,10 @@ k_adj_seed(const CavParams* __restrict__ cavp, const char* __restrict__ state,
   const int64_t pl = c.plane;
   const View<P> st = view<P>(state, c, FLOW);
   const AdjView<R> lv = adj_view<R>(lam, pl, FLOW);
-  double h = static_cast<double>(st.g0[cell]);
+  R g[7];
 #pragma unroll
-  for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(st.g[(a - 1) * pl + cell]));
+  for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
+  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(moving_sum(g));
   const double dfl = (h > c.hs && h < c.hl) ? c.inv_dh : 0.0;
   const R v = static_cast<R>(scale * dfl);
 #pragma unroll
@@ -405,9 +404,10 @@ k_adj_T0(const CavParams* __restrict__ cavp, const char* __restrict__ state0,
   const int64_t pl = c.plane;
   const View<P> st = view<P>(state0, c, FLOW);
   const AdjView<R> lv = adj_view<R>(lam, pl, FLOW);
-  double h = static_cast<double>(st.g0[cell]);
+  R g[7];
 #pragma unroll
-  for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(st.g[(a - 1) * pl + cell]));
+  for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
+  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(moving_sum(g));
   const double dh0 = h <= c.hs ? c.cp_s : c.cp_l;
   double s = 0.0;
 #pragma unroll

@@ -9,6 +9,17 @@ namespace lbpc {
 enum Prec { P64 = 0, P32 = 1, P16 = 2, PB16 = 3 };
 enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_ADIABATIC = 2 };
 
+// Per-cavity constants in the compute type of a kernel (precomputed on the
+// host so that kernels do not convert them per workgroup).
+template <class R> struct Pars {
+  R fshift, g_beta_rho0, T_ref;
+  R s_nu, s_e, s_eps, s_q, s_pi, s_t;
+  R lam_s, dlam, inv_rcw;       // lambda(f_l) = lam_s + f_l dlam
+  R cp_s, dcp;                  // C_p(f_l) = cp_s + f_l dcp
+  R w3, w21, whalf, wabb;       // 3, 21, 1/2 and 1 times omega_T C_p,ref
+  R sig_ovr[7];
+};
+
 // Per-cavity constants, read by every workgroup of that cavity through scalar
 // loads (the cavity index of a tile is uniform across the workgroup).
 struct alignas(16) CavParams {
@@ -32,7 +43,13 @@ struct alignas(16) CavParams {
   // flow
   double s_nu, s_e, s_eps, s_q, s_pi, s_t, g_beta_rho0, T_ref;
   double fshift;                // rho0 for shifted storage, 0 for raw FP64
+  Pars<float> pf;               // the constants above in FP32
+  Pars<double> pd;              // and in FP64
 };
+
+template <class R> __host__ __device__ inline const Pars<R>& pars(const CavParams& c);
+template <> __host__ __device__ inline const Pars<float>& pars<float>(const CavParams& c) { return c.pf; }
+template <> __host__ __device__ inline const Pars<double>& pars<double>(const CavParams& c) { return c.pd; }
 
 // Device-side budget record of one cavity.
 struct alignas(16) BudgetRec {

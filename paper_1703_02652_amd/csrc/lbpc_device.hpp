@@ -57,6 +57,18 @@ template <> __device__ __forceinline__ __bf16 ld_stream<__bf16>(const __bf16* p)
   return __builtin_bit_cast(__bf16, b);
 }
 
+// Element i of a plane whose base is the same for the whole wavefront: the
+// byte offset is formed in 32 bits (cells per cavity < 2^29, 8-byte elements
+// at most), which lets the loads and stores use a scalar base address plus a
+// 32-bit vector offset.
+template <class S> __device__ __forceinline__ S ld_off(const S* base, uint32_t i) {
+  return ld_stream(reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) +
+                                              i * static_cast<uint32_t>(sizeof(S))));
+}
+template <class S> __device__ __forceinline__ void st_off(S* base, uint32_t i, S v) {
+  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + i * static_cast<uint32_t>(sizeof(S))) = v;
+}
+
 template <int P> struct View {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
@@ -163,6 +175,13 @@ __device__ __forceinline__ void phase_rule(const CavParams& c, double h, double&
   }
 }
 
+// Sum of the six moving enthalpy populations (compute type) and h = g_0 + that
+// sum in FP64.  Every kernel that needs h of a cell goes through this, so the
+// step, its adjoint and the diagnostics take the same phase branch.
+template <class R> __device__ __forceinline__ R moving_sum(const R* g) {
+  return ((g[1] + g[2]) + (g[3] + g[4])) + (g[5] + g[6]);
+}
+
 // Macroscopic flow variables and forces of one cell (Eq. (55), (56)) with the
 // solid-region forcing u = f_l j / rho, j = sum f e + F_b / 2; d holds the
 // stored deviations f - fshift w.
@@ -183,11 +202,12 @@ __device__ __forceinline__ FlowMacro<R> flow_macro(const CavParams& c, const R* 
     if (Q19Z[a] != 0) jz += Q19Z[a] > 0 ? d[a] : -d[a];
   }
   m.dr = dr;
-  m.rho = static_cast<R>(c.fshift) + dr;
+  const Pars<R>& k = pars<R>(c);
+  m.rho = k.fshift + dr;
   m.jx = jx;
   m.jy = jy;
   m.jz0 = jz;
-  const R Fb = static_cast<R>(c.g_beta_rho0) * (T - static_cast<R>(c.T_ref));
+  const R Fb = k.g_beta_rho0 * (T - k.T_ref);
   const R jzb = jz + static_cast<R>(0.5) * Fb;
   const R irho = static_cast<R>(1) / m.rho;
   m.ux = fl * jx * irho;
@@ -232,8 +252,9 @@ __device__ __forceinline__ void flow_collide(const CavParams& c, R* d, const Flo
   const R rho = q.rho, ux = q.ux, uy = q.uy, uz = q.uz, Fx = q.Fx, Fy = q.Fy, Fz = q.Fz;
   const R u2 = ux * ux + uy * uy + uz * uz;
   const R Fu = Fx * ux + Fy * uy + Fz * uz;
-  const R s_e = static_cast<R>(c.s_e), s_eps = static_cast<R>(c.s_eps), s_q = static_cast<R>(c.s_q);
-  const R s_nu = static_cast<R>(c.s_nu), s_pi = static_cast<R>(c.s_pi), s_t = static_cast<R>(c.s_t);
+  const Pars<R>& pk = pars<R>(c);
+  const R s_e = pk.s_e, s_eps = pk.s_eps, s_q = pk.s_q;
+  const R s_nu = pk.s_nu, s_pi = pk.s_pi, s_t = pk.s_t;
   const R half = static_cast<R>(0.5), one = static_cast<R>(1);
   const R k_e = one - half * s_e, k_eps = one - half * s_eps, k_q = one - half * s_q;
   const R k_nu = one - half * s_nu, k_pi = one - half * s_pi;
@@ -303,8 +324,9 @@ __device__ __forceinline__ void flow_collide(const CavParams& c, R* d, const Flo
 // + 1/2 with chi = lambda(f_l) / (rho0 C_p,ref) (Eq. (20), (34)).
 template <class R>
 __device__ __forceinline__ R sigma_chi(const CavParams& c, R fl) {
-  const R lam = static_cast<R>(c.lam_s) + fl * static_cast<R>(c.lam_l - c.lam_s);
-  return static_cast<R>(1) / (lam * static_cast<R>(c.inv_rcw) + static_cast<R>(0.5));
+  const Pars<R>& k = pars<R>(c);
+  const R lam = k.lam_s + fl * k.dlam;
+  return static_cast<R>(1) / (lam * k.inv_rcw + static_cast<R>(0.5));
 }
 
 // MRT rates (Eq. (23), (47)): sigma_1..3 = sigma_chi, sigma_4..6 = 2 - sigma_chi,
@@ -316,7 +338,7 @@ __device__ __forceinline__ void mrt_rates(const CavParams& c, R sig, R* r) {
   if (c.has_override) {
 #pragma unroll
     for (int k = 1; k < 7; ++k)
-      if (!isnan(c.sig_ovr[k])) r[k] = static_cast<R>(c.sig_ovr[k]);
+      if (!isnan(c.sig_ovr[k])) r[k] = pars<R>(c).sig_ovr[k];
   }
 }
 
@@ -333,7 +355,7 @@ __device__ __forceinline__ R enth_collide_mrt(const CavParams& c, R* g, R s6, R 
   const R b1 = r[1] * (g[1] - g[2] - qT * ux) * static_cast<R>(0.5);
   const R b2 = r[2] * (g[3] - g[4] - qT * uy) * static_cast<R>(0.5);
   const R b3 = r[3] * (g[5] - g[6] - qT * uz) * static_cast<R>(0.5);
-  const R b4 = r[4] * (static_cast<R>(-7) * s6 + static_cast<R>(21.0 * c.omega_T * c.cp_ref) * T) *
+  const R b4 = r[4] * (static_cast<R>(-7) * s6 + pars<R>(c).w21 * T) *
                static_cast<R>(1.0 / 42.0);
   const R g12 = g[1] + g[2], g34 = g[3] + g[4], g56 = g[5] + g[6];
   const R b5 = r[5] * (static_cast<R>(2) * g12 - (g34 + g56)) * static_cast<R>(1.0 / 12.0);
@@ -356,9 +378,9 @@ __device__ __forceinline__ R enth_collide_mrt(const CavParams& c, R* g, R s6, R 
 template <class R>
 __device__ __forceinline__ R enth_collide_srt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
                                               R uy, R uz, R inv_tau) {
-  const R wT = static_cast<R>(0.5 * c.omega_T * c.cp_ref) * T;
+  const R wT = pars<R>(c).whalf * T;
   const R hq = static_cast<R>(0.5) * cp * T;
-  const R dg0 = -inv_tau * (static_cast<R>(3.0 * c.omega_T * c.cp_ref) * T - s6);
+  const R dg0 = -inv_tau * (pars<R>(c).w3 * T - s6);
   g[1] -= inv_tau * (g[1] - (wT + hq * ux));
   g[2] -= inv_tau * (g[2] - (wT - hq * ux));
   g[3] -= inv_tau * (g[3] - (wT + hq * uy));
@@ -469,35 +491,35 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
       const View<P> in = view<P>(src, c, FLOW);
       const View<P> out = view<P>(dst, c, FLOW);
       const int64_t pl = c.plane;
+      const uint32_t ucell = static_cast<uint32_t>(cell);
       R d[19];
       R g[7];
       if (FLOW) {
 #pragma unroll
-        for (int a = 0; a < 19; ++a) d[a] = dec(ld_stream(in.f + a * pl + cell));
+        for (int a = 0; a < 19; ++a) d[a] = dec(ld_off(in.f + a * pl, ucell));
       }
-      const double g0d = ld_stream(in.g0 + cell);
+      const double g0d = ld_off(in.g0, ucell);
       g[0] = static_cast<R>(g0d);
 #pragma unroll
-      for (int a = 1; a < 7; ++a) g[a] = dec(ld_stream(in.g + (a - 1) * pl + cell));
+      for (int a = 1; a < 7; ++a) g[a] = dec(ld_off(in.g + (a - 1) * pl, ucell));
 
       if (status[tl.x]) {  // frozen cavity: keep the state as it is
         if (FLOW) {
 #pragma unroll
-          for (int a = 0; a < 19; ++a) out.f[a * pl + cell] = enc<S>(d[a]);
+          for (int a = 0; a < 19; ++a) st_off(out.f + a * pl, ucell, enc<S>(d[a]));
         }
-        out.g0[cell] = g0d;
+        st_off(out.g0, ucell, g0d);
 #pragma unroll
-        for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(g[a]);
+        for (int a = 1; a < 7; ++a) st_off(out.g + (a - 1) * pl, ucell, enc<S>(g[a]));
       } else {
-        // enthalpy -> (T, f_l) in FP64
-        double s6d = 0.0;
-#pragma unroll
-        for (int a = 1; a < 7; ++a) s6d += static_cast<double>(g[a]);
-        const double hd = g0d + s6d;
+        // enthalpy -> (T, f_l) in FP64 (the moving populations are small; their
+        // sum is formed in the compute type)
+        const R s6 = moving_sum(g);
+        const double hd = g0d + static_cast<double>(s6);
         double Td, fld;
         phase_rule(c, hd, Td, fld);
-        const R T = static_cast<R>(Td), fl = static_cast<R>(fld), s6 = static_cast<R>(s6d);
-        const R cp = static_cast<R>(c.cp_s) + fl * static_cast<R>(c.cp_l - c.cp_s);
+        const R T = static_cast<R>(Td), fl = static_cast<R>(fld);
+        const R cp = pars<R>(c).cp_s + fl * pars<R>(c).dcp;
         R ux = 0, uy = 0, uz = 0;
         double rhod = 0.0;
         bool bad = !isfinite(hd);
@@ -517,31 +539,31 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         // stream: push every post-collision population along its link
         const Site s = make_site(c, cell);
         if (FLOW) {
-          out.f[cell] = enc<S>(d[0]);
+          st_off(out.f, ucell, enc<S>(d[0]));
 #pragma unroll
           for (int a = 1; a < 19; ++a) {
             int face;
             const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
-            if (face < 0) out.f[a * pl + to] = enc<S>(d[a]);
-            else out.f[Q19OPP[a] * pl + cell] = enc<S>(d[a]);  // halfway bounce-back
+            if (face < 0) st_off(out.f + a * pl, static_cast<uint32_t>(to), enc<S>(d[a]));
+            else st_off(out.f + Q19OPP[a] * pl, ucell, enc<S>(d[a]));  // halfway bounce-back
           }
         }
-        out.g0[cell] = g0d + static_cast<double>(dg0);
+        st_off(out.g0, ucell, g0d + static_cast<double>(dg0));
         double flux = 0.0;
 #pragma unroll
         for (int a = 1; a < 7; ++a) {
           int face;
           const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
           if (face < 0) {
-            out.g[(a - 1) * pl + to] = enc<S>(g[a]);
+            st_off(out.g + (a - 1) * pl, static_cast<uint32_t>(to), enc<S>(g[a]));
           } else if (c.bc[face] == BC_DIRICHLET) {
             // anti-bounce-back: g_abar(x) = -g*_a(x) + 2 w C_p,ref T_w
             const double Tw = c.tw[c.twface[face] + face_node(c, s, face)];
-            const R back = -g[a] + static_cast<R>(c.omega_T * c.cp_ref) * static_cast<R>(Tw);
-            out.g[(Q7OPP[a] - 1) * pl + cell] = enc<S>(back);
+            const R back = -g[a] + pars<R>(c).wabb * static_cast<R>(Tw);
+            st_off(out.g + (Q7OPP[a] - 1) * pl, ucell, enc<S>(back));
             flux += static_cast<double>(back) - static_cast<double>(g[a]);
           } else {
-            out.g[(Q7OPP[a] - 1) * pl + cell] = enc<S>(g[a]);  // adiabatic
+            st_off(out.g + (Q7OPP[a] - 1) * pl, ucell, enc<S>(g[a]));  // adiabatic
           }
         }
         acc[0] = hd;
@@ -608,13 +630,12 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
 #pragma unroll
         for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
       }
-      g[0] = static_cast<R>(in.g0[cell]);
+      const double g0d = in.g0[cell];
+      g[0] = static_cast<R>(g0d);
 #pragma unroll
       for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
-      double s6 = 0.0;
-#pragma unroll
-      for (int a = 1; a < 7; ++a) s6 += static_cast<double>(g[a]);
-      const double h = static_cast<double>(g[0]) + s6;
+      const R s6 = moving_sum(g);
+      const double h = g0d + static_cast<double>(s6);
       double T, fl;
       phase_rule(c, h, T, fl);
       double rho = 0.0;
@@ -632,8 +653,8 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         const R cp = static_cast<R>(c.cp_s) + flr * static_cast<R>(c.cp_l - c.cp_s);
         const R sig = sigma_chi<R>(c, flr);
         const R ux = FLOW ? q.ux : R(0), uy = FLOW ? q.uy : R(0), uz = FLOW ? q.uz : R(0);
-        if (MRT) enth_collide_mrt<R>(c, g, static_cast<R>(s6), Tr, cp, ux, uy, uz, sig);
-        else enth_collide_srt<R>(c, g, static_cast<R>(s6), Tr, cp, ux, uy, uz, sig);
+        if (MRT) enth_collide_mrt<R>(c, g, s6, Tr, cp, ux, uy, uz, sig);
+        else enth_collide_srt<R>(c, g, s6, Tr, cp, ux, uy, uz, sig);
         const double Tw = c.tw[c.twface[0] + face_node(c, st, 0)];
         acc[3] = c.omega_T * c.cp_ref * Tw - 2.0 * static_cast<double>(g[2]);
       }
@@ -657,9 +678,10 @@ k_fields(const CavParams* __restrict__ cavp, const char* __restrict__ src, uint3
   if (cell >= c.n) return;
   const View<P> in = view<P>(src, c, FLOW);
   const int64_t pl = c.plane;
-  double h = static_cast<double>(in.g0[cell]);
+  R g[7];
 #pragma unroll
-  for (int a = 1; a < 7; ++a) h += static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+  for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
+  const double h = static_cast<double>(in.g0[cell]) + static_cast<double>(moving_sum(g));
   double T, fl;
   phase_rule(c, h, T, fl);
   double rho = 0.0, u[3] = {0.0, 0.0, 0.0};

@@ -252,6 +252,28 @@ void magic(uint32_t d, uint64_t& m, uint32_t& s) {
   s = 32 + l;
 }
 
+template <class R> void fill_pars(const CavParams& p, Pars<R>& q) {
+  q.fshift = static_cast<R>(p.fshift);
+  q.g_beta_rho0 = static_cast<R>(p.g_beta_rho0);
+  q.T_ref = static_cast<R>(p.T_ref);
+  q.s_nu = static_cast<R>(p.s_nu);
+  q.s_e = static_cast<R>(p.s_e);
+  q.s_eps = static_cast<R>(p.s_eps);
+  q.s_q = static_cast<R>(p.s_q);
+  q.s_pi = static_cast<R>(p.s_pi);
+  q.s_t = static_cast<R>(p.s_t);
+  q.lam_s = static_cast<R>(p.lam_s);
+  q.dlam = static_cast<R>(p.lam_l - p.lam_s);
+  q.inv_rcw = static_cast<R>(p.inv_rcw);
+  q.cp_s = static_cast<R>(p.cp_s);
+  q.dcp = static_cast<R>(p.cp_l - p.cp_s);
+  q.w3 = static_cast<R>(3.0 * p.omega_T * p.cp_ref);
+  q.w21 = static_cast<R>(21.0 * p.omega_T * p.cp_ref);
+  q.whalf = static_cast<R>(0.5 * p.omega_T * p.cp_ref);
+  q.wabb = static_cast<R>(p.omega_T * p.cp_ref);
+  for (int k = 0; k < 7; ++k) q.sig_ovr[k] = static_cast<R>(p.sig_ovr[k]);
+}
+
 CavParams make_params(const lbpc_config& c, const Layout& L, int i, const double* d_tw) {
   CavParams p;
   std::memset(&p, 0, sizeof(p));
@@ -297,6 +319,8 @@ CavParams make_params(const lbpc_config& c, const Layout& L, int i, const double
   p.g_beta_rho0 = c.g_beta * c.rho0;
   p.T_ref = c.T_ref;
   p.fshift = c.precision == LBPC_FP64 ? 0.0 : c.rho0;
+  fill_pars(p, p.pf);
+  fill_pars(p, p.pd);
   return p;
 }
 
