@@ -77,7 +77,7 @@ enum {
  *   F_z = rho0 g_beta (T - T_ref) (Eq. (55)).  flow = 0 runs the enthalpy
  *   distribution alone with u = 0. */
 typedef struct lbpc_config {
-  int32_t nx, ny, nz;
+  int32_t nx, ny, nz;   /* each >= 1; nx*ny*nz below 2^29 cells per cavity */
   int32_t flow;         /* 0: enthalpy only, 1: coupled D3Q19 flow */
   int32_t enth_model;   /* LBPC_SRT or LBPC_MRT */
   int32_t precision;    /* LBPC_FP64 ... LBPC_BF16S; same for every cavity of a batch */

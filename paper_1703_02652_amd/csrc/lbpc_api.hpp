@@ -29,6 +29,7 @@ struct alignas(16) CavParams {
   int32_t tile0, ntiles;        // this cavity's tiles in the tile queue
   int32_t chunk0, nchunks;      // this cavity's reduction chunks (runs of tiles)
   int32_t has_override;         // any finite sigma_override entry
+  int32_t walls_only;           // no periodic face: every link either stays inside or hits a wall
   uint64_t div_nx_m, div_nxy_m; // magic multipliers: q = (i * m) >> s
   uint32_t div_nx_s, div_nxy_s;
   int64_t off;                  // byte offset of the cavity inside a state region

@@ -57,16 +57,50 @@ template <> __device__ __forceinline__ __bf16 ld_stream<__bf16>(const __bf16* p)
   return __builtin_bit_cast(__bf16, b);
 }
 
-// Element i of a plane whose base is the same for the whole wavefront: the
-// byte offset is formed in 32 bits (cells per cavity < 2^29, 8-byte elements
-// at most), which lets the loads and stores use a scalar base address plus a
-// 32-bit vector offset.
-template <class S> __device__ __forceinline__ S ld_off(const S* base, uint32_t i) {
-  return ld_stream(reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) +
-                                              i * static_cast<uint32_t>(sizeof(S))));
+// Population planes through buffer resources (step kernel).  A plane is
+// addressed by a resource holding its base and byte size (scalar registers)
+// and one 32-bit byte offset per lane.  The hardware range check drops a store
+// whose offset is at or past the plane size, so a lane is masked out of a
+// store by giving it the offset kDrop.  Planes hold fewer than 2^29 cells of at
+// most 8 bytes, so every plane size stays below kDrop.
+constexpr uint32_t kDrop = 0xFFFFFFF0u;
+constexpr int kNonTemporal = 2;   // cache-policy bits of a streaming load
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
+  // word 3: raw access (no swizzle, stride 0) with a 32-bit data format
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes),
+                                           0x00020000);
 }
-template <class S> __device__ __forceinline__ void st_off(S* base, uint32_t i, S v) {
-  *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + i * static_cast<uint32_t>(sizeof(S))) = v;
+template <class S> __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <class S> __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, S v);
+template <> __device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                        r, static_cast<int>(off), 0, kNonTemporal));
+}
+template <> __device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                       r, static_cast<int>(off), 0, kNonTemporal));
+}
+template <> __device__ __forceinline__ _Float16 buf_ld<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(
+                                          r, static_cast<int>(off), 0, kNonTemporal));
+}
+template <> __device__ __forceinline__ __bf16 buf_ld<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(
+                                        r, static_cast<int>(off), 0, kNonTemporal));
+}
+template <> __device__ __forceinline__ void buf_st<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, static_cast<int>(off), 0, 0);
+}
+template <> __device__ __forceinline__ void buf_st<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, static_cast<int>(off), 0, 0);
+}
+template <> __device__ __forceinline__ void buf_st<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t off, _Float16 v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, static_cast<int>(off), 0, 0);
+}
+template <> __device__ __forceinline__ void buf_st<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t off, __bf16 v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, static_cast<int>(off), 0, 0);
 }
 
 template <int P> struct View {
@@ -145,6 +179,12 @@ __device__ __forceinline__ int32_t link_target(const CavParams& c, const Site& s
   if (ez > 0 && s.hz) { if (c.bc[5] == BC_PERIODIC) idx -= c.n; else face = 5; }
   if (ez < 0 && s.lz) { if (c.bc[4] == BC_PERIODIC) idx += c.n; else face = 4; }
   return idx;
+}
+
+// True when the link (ex, ey, ez) from s leaves the cavity (all faces walls).
+__device__ __forceinline__ bool hits_wall(const Site& s, int ex, int ey, int ez) {
+  return (ex > 0 && s.hx) || (ex < 0 && s.lx) || (ey > 0 && s.hy) || (ey < 0 && s.ly) ||
+         (ez > 0 && s.hz) || (ez < 0 && s.lz);
 }
 
 // Node of a face field seen by the cell at s: x faces [nz][ny], y faces
@@ -491,26 +531,30 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
       const View<P> in = view<P>(src, c, FLOW);
       const View<P> out = view<P>(dst, c, FLOW);
       const int64_t pl = c.plane;
-      const uint32_t ucell = static_cast<uint32_t>(cell);
+      const uint32_t pb = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(S));
+      const uint32_t pb0 = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(S0));
+      const uint32_t oc = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
+      const uint32_t oc0 = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S0));
       R d[19];
       R g[7];
       if (FLOW) {
 #pragma unroll
-        for (int a = 0; a < 19; ++a) d[a] = dec(ld_off(in.f + a * pl, ucell));
+        for (int a = 0; a < 19; ++a) d[a] = dec(buf_ld<S>(plane_rsrc(in.f + a * pl, pb), oc));
       }
-      const double g0d = ld_off(in.g0, ucell);
+      const double g0d = buf_ld<S0>(plane_rsrc(in.g0, pb0), oc0);
       g[0] = static_cast<R>(g0d);
 #pragma unroll
-      for (int a = 1; a < 7; ++a) g[a] = dec(ld_off(in.g + (a - 1) * pl, ucell));
+      for (int a = 1; a < 7; ++a) g[a] = dec(buf_ld<S>(plane_rsrc(in.g + (a - 1) * pl, pb), oc));
 
       if (status[tl.x]) {  // frozen cavity: keep the state as it is
         if (FLOW) {
 #pragma unroll
-          for (int a = 0; a < 19; ++a) st_off(out.f + a * pl, ucell, enc<S>(d[a]));
+          for (int a = 0; a < 19; ++a) buf_st<S>(plane_rsrc(out.f + a * pl, pb), oc, enc<S>(d[a]));
         }
-        st_off(out.g0, ucell, g0d);
+        buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, g0d);
 #pragma unroll
-        for (int a = 1; a < 7; ++a) st_off(out.g + (a - 1) * pl, ucell, enc<S>(g[a]));
+        for (int a = 1; a < 7; ++a)
+          buf_st<S>(plane_rsrc(out.g + (a - 1) * pl, pb), oc, enc<S>(g[a]));
       } else {
         // enthalpy -> (T, f_l) in FP64 (the moving populations are small; their
         // sum is formed in the compute type)
@@ -536,34 +580,68 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         const R dg0 = MRT ? enth_collide_mrt<R>(c, g, s6, T, cp, ux, uy, uz, sig)
                           : enth_collide_srt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
 
-        // stream: push every post-collision population along its link
+        // stream: push every post-collision population along its link.  With
+        // walls on all six faces a link either stays inside the cavity (target
+        // = this cell + a shift that is the same for the whole cavity) or hits
+        // a wall; periodic faces go through link_target.
         const Site s = make_site(c, cell);
         if (FLOW) {
-          st_off(out.f, ucell, enc<S>(d[0]));
+          buf_st<S>(plane_rsrc(out.f, pb), oc, enc<S>(d[0]));
+          if (c.walls_only) {
 #pragma unroll
-          for (int a = 1; a < 19; ++a) {
-            int face;
-            const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
-            if (face < 0) st_off(out.f + a * pl, static_cast<uint32_t>(to), enc<S>(d[a]));
-            else st_off(out.f + Q19OPP[a] * pl, ucell, enc<S>(d[a]));  // halfway bounce-back
+            for (int a = 1; a < 19; ++a) {
+              const S v = enc<S>(d[a]);
+              const bool wall = hits_wall(s, Q19X[a], Q19Y[a], Q19Z[a]);
+              const int32_t shift = Q19X[a] + Q19Y[a] * c.nx + Q19Z[a] * c.nxy;
+              const uint32_t to = oc + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(S));
+              buf_st<S>(plane_rsrc(out.f + a * pl, pb), wall ? kDrop : to, v);
+              if (wall) buf_st<S>(plane_rsrc(out.f + Q19OPP[a] * pl, pb), oc, v);  // halfway bounce-back
+            }
+          } else {
+#pragma unroll
+            for (int a = 1; a < 19; ++a) {
+              int face;
+              const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
+              const S v = enc<S>(d[a]);
+              if (face < 0)
+                buf_st<S>(plane_rsrc(out.f + a * pl, pb),
+                          static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(S)), v);
+              else
+                buf_st<S>(plane_rsrc(out.f + Q19OPP[a] * pl, pb), oc, v);  // halfway bounce-back
+            }
           }
         }
-        st_off(out.g0, ucell, g0d + static_cast<double>(dg0));
+        buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, g0d + static_cast<double>(dg0));
         double flux = 0.0;
 #pragma unroll
         for (int a = 1; a < 7; ++a) {
+          const auto rs_out = plane_rsrc(out.g + (a - 1) * pl, pb);
+          const auto rs_back = plane_rsrc(out.g + (Q7OPP[a] - 1) * pl, pb);
           int face;
-          const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
-          if (face < 0) {
-            st_off(out.g + (a - 1) * pl, static_cast<uint32_t>(to), enc<S>(g[a]));
-          } else if (c.bc[face] == BC_DIRICHLET) {
-            // anti-bounce-back: g_abar(x) = -g*_a(x) + 2 w C_p,ref T_w
-            const double Tw = c.tw[c.twface[face] + face_node(c, s, face)];
-            const R back = -g[a] + pars<R>(c).wabb * static_cast<R>(Tw);
-            st_off(out.g + (Q7OPP[a] - 1) * pl, ucell, enc<S>(back));
-            flux += static_cast<double>(back) - static_cast<double>(g[a]);
+          bool wall;
+          if (c.walls_only) {
+            face = (a & 1) ? a : a - 2;  // +x -> x+ face (1), -x -> x- face (0), ...
+            wall = hits_wall(s, Q7X[a], Q7Y[a], Q7Z[a]);
+            const int32_t shift = Q7X[a] + Q7Y[a] * c.nx + Q7Z[a] * c.nxy;
+            const uint32_t to = oc + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(S));
+            buf_st<S>(rs_out, wall ? kDrop : to, enc<S>(g[a]));
           } else {
-            st_off(out.g + (Q7OPP[a] - 1) * pl, ucell, enc<S>(g[a]));  // adiabatic
+            const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
+            wall = face >= 0;
+            if (!wall)
+              buf_st<S>(rs_out, static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(S)),
+                        enc<S>(g[a]));
+          }
+          if (wall) {
+            if (c.bc[face] == BC_DIRICHLET) {
+              // anti-bounce-back: g_abar(x) = -g*_a(x) + 2 w C_p,ref T_w
+              const double Tw = c.tw[c.twface[face] + face_node(c, s, face)];
+              const R back = -g[a] + pars<R>(c).wabb * static_cast<R>(Tw);
+              buf_st<S>(rs_back, oc, enc<S>(back));
+              flux += static_cast<double>(back) - static_cast<double>(g[a]);
+            } else {
+              buf_st<S>(rs_back, oc, enc<S>(g[a]));  // adiabatic
+            }
           }
         }
         acc[0] = hd;

@@ -21,6 +21,10 @@ constexpr int kMinTile = 64;        // smallest tile: one wavefront
 constexpr int kMaxTile = 256;       // largest tile: __launch_bounds__ of the kernels
 constexpr int kChunk = 256;         // tiles per first-pass reduction workgroup
 constexpr int kXcd = 8;             // XCDs of an MI355X: runs of the XCD-contiguous order
+// Cells added to every population plane: keeps the planes of a cavity from
+// starting at power-of-two distances (2^21 or 2^24 cells for 128^3 / 256^3),
+// where the 26 concurrent plane streams fall on the same HBM channels.
+constexpr int64_t kPlanePad = 256;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
@@ -149,7 +153,8 @@ bool validate(const lbpc_config* cfgs, int batch, std::string& err) {
     };
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) return bad("nx, ny, nz must be >= 1");
     const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
-    if (n >= (int64_t(1) << 30)) return bad("too many cells (limit 2^30 per cavity)");
+    // kernels address a plane with 32-bit byte offsets of elements up to 8 bytes
+    if (n + 128 + kPlanePad > (int64_t(1) << 29)) return bad("too many cells (limit 2^29 per cavity)");
     total += n;
     if (c.flow != 0 && c.flow != 1) return bad("flow must be 0 or 1");
     if (c.enth_model != LBPC_SRT && c.enth_model != LBPC_MRT) return bad("enth_model must be SRT or MRT");
@@ -200,7 +205,7 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   for (int i = 0; i < batch; ++i) {
     const lbpc_config& c = cfgs[i];
     const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
-    const int64_t plane = (n + 127) / 128 * 128;
+    const int64_t plane = (n + 127) / 128 * 128 + kPlanePad;
     L.ncell.push_back(n);
     L.plane.push_back(plane);
     L.off.push_back(off);
@@ -282,7 +287,11 @@ CavParams make_params(const lbpc_config& c, const Layout& L, int i, const double
   p.nz = c.nz;
   p.n = static_cast<int32_t>(L.ncell[i]);
   p.nxy = c.nx * c.ny;
-  for (int f = 0; f < 6; ++f) p.bc[f] = c.face_bc[f];
+  p.walls_only = 1;
+  for (int f = 0; f < 6; ++f) {
+    p.bc[f] = c.face_bc[f];
+    if (c.face_bc[f] == LBPC_PERIODIC) p.walls_only = 0;
+  }
   magic(static_cast<uint32_t>(c.nx), p.div_nx_m, p.div_nx_s);
   magic(static_cast<uint32_t>(p.nxy), p.div_nxy_m, p.div_nxy_s);
   p.off = L.off[i];
