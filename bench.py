@@ -107,14 +107,18 @@ def precision_errors(n=256, steps=1000):
     return dict(cells=n**3, steps=steps, errors=out)
 
 
-def cpu_baseline(cfg, target_s=10.0, max_steps=40):
-    """The FP64 CPU oracle on the same workload, a bounded number of steps."""
+def cpu_baseline(cfg, target_s=12.0, max_steps=400):
+    """The FP64 CPU oracle on the same workload, a bounded number of steps
+    (about target_s seconds, sized from a short probe after one warm-up step)."""
     import oracle
-    st = oracle.init_state(cfg)
-    t = time.perf_counter()
-    st = oracle.run(cfg, st, 1)
-    t1 = time.perf_counter() - t
-    n = int(max(1, min(max_steps, target_s / max(t1, 1e-3))))
+    st = oracle.run(cfg, oracle.init_state(cfg), 1)
+    probe = []
+    for k in (2, 6):   # per-step cost without the per-call state conversion
+        t = time.perf_counter()
+        st = oracle.run(cfg, st, k)
+        probe.append(time.perf_counter() - t)
+    t1 = max((probe[1] - probe[0]) / 4, 1e-3)
+    n = int(max(1, min(max_steps, target_s / t1)))
     t = time.perf_counter()
     oracle.run(cfg, st, n)
     dt = time.perf_counter() - t

@@ -157,14 +157,17 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
                     int32_t* graph_steps, int32_t* xcd_runs);
 
 /* Time every candidate launch configuration (tile size, persistent grid, XCD
- * order) with real alternating steps from the current state and keep the
+ * order) with real alternating steps from the current state (without budget
+ * partials) and keep the
  * fastest.  The state is copied to host memory first and restored afterwards,
  * so tuning does not advance the run.  host_ms_out (nullable) receives the
  * best average step-kernel time in milliseconds.  Synchronises the stream. */
 int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 
-/* Advance nsteps with a HIP event pair around each step-kernel launch; the
- * mean kernel time in milliseconds goes to host_ms_out.  Synchronises. */
+/* Advance nsteps with eager step-kernel launches whose start and end events
+ * are recorded by the dispatch itself (hipExtLaunchKernel), on the library's
+ * stream; the mean kernel time in milliseconds goes to host_ms_out.
+ * Synchronises. */
 int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
 
 /* Discrete adjoint of the loss L = sum over cells of f_l at the final step

@@ -77,6 +77,8 @@ struct StepArgs {
   int xcd;                      // > 1: XCD-contiguous tile order (grid rounded up)
   int flow, mrt;
   hipStream_t stream;
+  hipEvent_t ev_start = nullptr;  // non-null: the dispatch itself records start and end
+  hipEvent_t ev_stop = nullptr;
 };
 
 struct AdjArgs {
