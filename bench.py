@@ -154,6 +154,63 @@ def adjoint_ratio(prec, n=96, steps=200, every=100):
                 total_over_forward=(t2 - t0) / t_fwd)
 
 
+def two_d_validations():
+    """Sec. 3.2 at the paper's sizes on y-periodic slabs, FP32: solidification
+    in a corner (400 x 400, to Fo = 0.25 with l_c = 400) and melting with
+    convection (Table 1 on a 128 x 128 slab, Nu of Eq. (65) at the hot wall
+    averaged over ten samples in the last 2 % of the steps before Fo = 4, 10,
+    20, and the mean liquid fraction)."""
+    import math
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1703_02652_amd import Cavity
+    out = {}
+    n, chi = 400, 0.2
+    cfg = W.corner_solidification(n, chi=chi, precision=W.FP32)
+    cav = Cavity(cfg, T0=np.full((n, 1, n), 0.3), device="cuda")
+    cav.autotune(5)
+    steps = int(round(0.25 * n * n / chi))
+    dt = timed_steps(cav, steps)
+    fl = cav.fields(names=("fl",))["fl"][:, 0, :].cpu().numpy()   # [z][x]
+    diag = float(sum(1.0 - fl[i, i] for i in range(n))) * math.sqrt(2.0)
+    out["corner400_fp32"] = dict(
+        cells=n * n, steps=steps, fo=0.25, mlups=n * n * steps / dt / 1e6,
+        launch=list(cav.get_launch()), liquid_fraction=round(float(fl.mean()), 5),
+        solid_depth_mid_row=round(float((1.0 - fl[n // 2]).sum()), 3),
+        solid_depth_bisector=round(diag, 3),
+        symmetry_max_dfl=float(np.abs(fl - fl.T).max()))
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+
+    n = 128
+    cfg = W.convection_2d(n, precision=W.FP32)
+    chi = cfg["lambda_l"] / (cfg["rho0"] * cfg["cp_ref"])
+    cav = Cavity(cfg, device="cuda")
+    cav.autotune(5)
+    rec, done, t_run = [], 0, 0.0
+    for fo in (4.0, 10.0, 20.0):
+        t = int(round(fo * n * n / chi))
+        w = max(10, t // 50) // 10 * 10
+        t_run += timed_steps(cav, t - w - done)
+        nus = []
+        for _ in range(10):   # hot-wall inflow only (the cold face may see outflow)
+            t_run += timed_steps(cav, w // 10)
+            nus.append(cav.nusselt())
+        done = t
+        rec.append(dict(fo=fo, steps=t, nusselt=round(float(np.mean(nus)), 4),
+                        mean_fl=round(float(cav.budgets()[0, 2]) / (n * n), 5)))
+    out["convection2d128_fp32"] = dict(cells=n * n, mlups=n * n * done / t_run / 1e6,
+                                       launch=list(cav.get_launch()), history=rec,
+                                       unstable=int(cav.status().max()))
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,11 +265,11 @@ def main():
     extras = {}
     if not args.no_extras:
         xs = max(50, args.steps // 5)
-        for name, prec in (("cavity256_fp32", W.FP32), ("cavity256_fp16s", W.FP16S),
-                           ("cavity256_bf16s", W.BF16S)):
-            c = W.precision_cavity(256, 0.02, precision=prec)
+        for name, xprec in (("cavity256_fp32", W.FP32), ("cavity256_fp16s", W.FP16S),
+                            ("cavity256_bf16s", W.BF16S)):
+            c = W.precision_cavity(256, 0.02, precision=xprec)
             cv, r = run_cavity(c, xs, 20, label=name)
-            r["hbm_frac"] = round(BYTES_PER_CELL[prec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
+            r["hbm_frac"] = round(BYTES_PER_CELL[xprec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
                                   / HBM_PEAK_GBS, 4)
             extras[name] = r
             cv.close()
@@ -248,6 +305,8 @@ def main():
         log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
         extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)
         log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
+        extras.update(two_d_validations())
+        log(f"[bench] 2D: {extras['corner400_fp32']} {extras['convection2d128_fp32']}")
 
     cpu = None
     if not args.no_cpu:

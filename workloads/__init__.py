@@ -138,6 +138,31 @@ def table2_case(case, precision=FP32, Ma=0.1):
     return cfg
 
 
+def corner_solidification(n=400, chi=0.2, precision=FP64, T0=0.3, T_wall=-1.0, Ste=4.0):
+    """2D solidification in a corner (Sec. 3.2.1) on an n x 1 x n slab in the xz
+    plane, periodic along y: liquid at T0 = 0.3 above T_f = T_m = 0, the faces
+    x = 0 and z = 0 held at T_l = -1 from t = 0, Ste = C_p (T_f - T_l) / L = 4,
+    equal solid and liquid properties, enthalpy only.  The quarter-infinite
+    domain is truncated at x = n and z = n with the far faces held at T0."""
+    latent = 1.0 * (0.0 - T_wall) / Ste
+    return base_config(n, 1, n, flow=0, enth_model=MRT, precision=precision,
+                       face_bc=[DIRICHLET, DIRICHLET, PERIODIC, PERIODIC, DIRICHLET, DIRICHLET],
+                       face_T=[T_wall, T0, 0.0, 0.0, T_wall, T0],
+                       lambda_s=chi, lambda_l=chi, latent=latent, T_m=0.0, nu=0.1, g_beta=0.0)
+
+
+def convection_2d(n=128, precision=FP32, Ra=2.5e4, Pr=0.02, Ste=0.01, Ma=0.1, buoyancy=True):
+    """2D melting with convection (Sec. 3.2.2, Table 1) on an n x 1 x n slab in
+    the xz plane, periodic along y: solid at T_m = 0, x = 0 at T_h = 1, x = n at
+    T_m, z faces adiabatic, no-slip; l_c = n.  buoyancy=False keeps g beta = 0
+    (pure conduction, the one-phase Neumann problem along x)."""
+    cfg = melting_cavity(n, Ra, Pr, Ste, precision=precision, Ma=Ma)
+    cfg.update(ny=1, face_bc=[DIRICHLET, DIRICHLET, PERIODIC, PERIODIC, ADIABATIC, ADIABATIC])
+    if not buoyancy:
+        cfg["g_beta"] = 0.0
+    return cfg
+
+
 def hot_wall_field(ny, nz, seed=1703, amp=0.05):
     """Hot-wall temperature field T_w(y, z) = 1 + U(-amp, amp); layout [z][y]."""
     rng = np.random.default_rng(seed)
