@@ -55,6 +55,8 @@ def test_version_and_validation_without_gpu(libpath):
     assert L.lbpc_workspace_bytes(make_configs([bad]), 1) == 0
     mixed = [good, dict(good, precision=W.FP64)]
     assert L.lbpc_workspace_bytes(make_configs(mixed), 2) == 0
+    assert L.lbpc_workspace_bytes(make_configs([good]), 0) == 0    # empty batch
+    assert L.lbpc_workspace_bytes(None, 1) == 0
     # 32-bit byte offsets of 8-byte elements bound a cavity to 2^29 cells
     assert L.lbpc_workspace_bytes(make_configs([dict(good, nx=812, ny=812, nz=812)]), 1) > 0
     assert L.lbpc_workspace_bytes(make_configs([dict(good, nx=813, ny=813, nz=813)]), 1) == 0

@@ -1,0 +1,72 @@
+"""Edge cases on the GPU: degenerate lattices (one cell, one-cell-thick
+dimensions with walls or periodic wrap) against the oracle from arbitrary
+states, and the full-size 256^3 cavity in the launch shape the benchmark
+tunes, in FP32 and shifted FP16 storage."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import W19, absdiff, make_cavity, random_walls, rel
+
+pytestmark = pytest.mark.gpu
+
+D, A, P = W.DIRICHLET, W.ADIABATIC, W.PERIODIC
+# (nx, ny, nz, faces): every link of a 1x1x1 cell hits a wall; thin dimensions
+# with walls on both sides; thin periodic dimensions wrap onto the cell itself
+DEGENERATE = [
+    (1, 1, 1, [D, A, D, A, A, D]),
+    (1, 5, 1, [D, D, P, P, A, A]),
+    (2, 1, 3, [A, D, P, P, D, A]),
+    (3, 2, 1, [P, P, D, D, A, A]),
+    (1, 1, 9, [P, P, P, P, D, A]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+@pytest.mark.parametrize("flow", [0, 1])
+def test_degenerate_lattices_match_oracle(case, flow):
+    nx, ny, nz, bc = DEGENERATE[case]
+    cfg = W.base_config(nx, ny, nz, flow=flow, enth_model=W.MRT, precision=W.FP64, face_bc=bc,
+                        face_T=[1.0, -0.4, 0.3, 0.7, 0.9, -0.2], g_beta=4e-3, latent=1.5,
+                        lambda_s=0.09, lambda_l=0.09, nu=0.04, cp_l=1.4)
+    f, g = W.random_populations(cfg, seed=300 + case, f_scale=W19)
+    walls = random_walls(cfg, seed=400 + case)
+    tw = W.wall_fields(cfg, walls)
+    cav = make_cavity(cfg, walls=walls)
+    cav.set_state(f, g)
+    cav.step(7)
+    st = oracle.run(cfg, (f if flow else None, g), 7, tw=tw)
+    fg, gg = cav.state()
+    print(f"{nx}x{ny}x{nz} flow={flow}: g {rel(gg, st[1]):.2e}"
+          + (f" f {rel(fg, st[0]):.2e}" if flow else ""))
+    assert rel(gg, st[1]) < 1e-12
+    if flow:
+        assert rel(fg, st[0]) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16S])
+def test_cavity256_full_size_one_step_against_oracle(prec):
+    """Full-size 256^3 precision cavity (Ra 1e6, Pr 0.02) in the launch shape the
+    benchmark tunes: after 100 steps the oracle's FP64 step from the GPU state
+    (decoded) agrees with the GPU's next state to the storage rounding."""
+    cfg = W.precision_cavity(256, 0.02, precision=prec)
+    cav = make_cavity(cfg)
+    cav.autotune(3)
+    cav.step(100)
+    f, g = cav.state()
+    st = (f.cpu().numpy(), g.cpu().numpy())
+    del f, g
+    cav.step(1)
+    f1, g1 = cav.state()
+    ref = oracle.run(dict(cfg, precision=W.FP64), st, 1)
+    dev = np.abs(ref[0] - W19.reshape(19, 1, 1, 1) * cfg["rho0"]).max()
+    ef, eg = absdiff(f1, ref[0]), absdiff(g1, ref[1])
+    print(f"256^3 {['fp64', 'fp32', 'fp16s'][prec]} one step (launch {cav.get_launch()}): "
+          f"max|df| {ef:.2e} (max deviation {dev:.2e}), max|dg| {eg:.2e}")
+    # shifted storage rounds the deviation f - w rho0 (FP32: 24 bits, FP16: 11)
+    # and g_1..6; observed FP32 6.7e-12 on a 1.9e-5 deviation, FP16 3e-8
+    bits = 20 if prec == W.FP32 else 10
+    assert ef < 2.0 ** -bits * dev + 1e-13
+    assert eg < 2.0 ** -bits * np.abs(ref[1][1:]).max()
+    assert abs(cav.budgets()[0, 1] / 256**3 - 1.0) < 1e-5
