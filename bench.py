@@ -305,6 +305,8 @@ def main():
         log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
         extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)
         log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
+        extras["adjoint96_fp32_every_step"] = adjoint_ratio(W.FP32, every=1)
+        log(f"[bench] adjoint fp32, a snapshot per step: {extras['adjoint96_fp32_every_step']}")
         extras.update(two_d_validations())
         log(f"[bench] 2D: {extras['corner400_fp32']} {extras['convection2d128_fp32']}")
 

@@ -179,7 +179,9 @@ int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
  *     populations).
  *   lbpc_adjoint_forward: run nsteps from the current state, storing
  *     checkpoints in dev_adj_ws; the state is left at the final step; the loss
- *     goes to host_loss (synchronises).
+ *     goes to host_loss (synchronises).  ckpt_every = 1 keeps every state
+ *     (nsteps regions: 96^3 x 2000 FP32 steps take 191 GB): each step writes
+ *     into its snapshot directly and the reverse sweep recomputes nothing.
  *   lbpc_adjoint_backward: reverse sweep with recomputation per segment; seed
  *     scales the loss (dL/dL = seed).  dev_dL_dTw: FP64, all six faces'
  *     node fields back to back (layout of lbpc_set_wall_T), zero on faces

@@ -993,11 +993,31 @@ int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t los
   int rc = flush(x);
   if (rc) return rc;
   const size_t rb = static_cast<size_t>(x->L.region_bytes);
-  for (int64_t s = 0; s < nsteps; s += every) {
-    HIPCHK(x, hipMemcpyAsync(a.ws + a.o_snap + rb * static_cast<size_t>(s / every),
-                             x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
-    rc = run_steps(x, std::min<int64_t>(every, nsteps - s));
-    if (rc) return rc;
+  if (every == 1) {
+    // a snapshot of every state: each step writes straight into the next
+    // snapshot slot (no copies; the backward sweep then recomputes nothing)
+    char* snap = a.ws + a.o_snap;
+    HIPCHK(x, hipMemcpyAsync(snap, x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
+    for (int64_t t = 0; t < nsteps; ++t) {
+      char* dst = t + 1 < nsteps ? snap + rb * static_cast<size_t>(t + 1) : x->region[x->cur ^ 1];
+      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * NPART;
+      // all partials only where a reduction closes (as the graphs do)
+      const int budget = (x->pending + 1 == kRing || t + 1 == nsteps) ? 2 : 1;
+      HIPCHK(x, dispatch_step(x, snap + rb * static_cast<size_t>(t), dst, part, budget, x->stream));
+      x->steps += 1;
+      if (++x->pending == kRing) {
+        rc = flush(x);
+        if (rc) return rc;
+      }
+    }
+    x->cur ^= 1;
+  } else {
+    for (int64_t s = 0; s < nsteps; s += every) {
+      HIPCHK(x, hipMemcpyAsync(a.ws + a.o_snap + rb * static_cast<size_t>(s / every),
+                               x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
+      rc = run_steps(x, std::min<int64_t>(every, nsteps - s));
+      if (rc) return rc;
+    }
   }
   a.end_step = x->steps;
   double b[6];

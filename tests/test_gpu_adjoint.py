@@ -168,3 +168,23 @@ def test_adjoint96_fd_check_full_size():
     print(f"96^3 L={L:.4f}; adjoint {g[:4]}; fd {fd[:4]}; max rel err {err.max():.2e}")
     torch.cuda.synchronize()
     assert err.max() < 1e-5
+
+
+def test_adjoint_with_a_snapshot_of_every_step_equals_segments():
+    """ckpt_every = 1 (every state kept, no recomputation) gives the same loss,
+    final state and gradient as checkpoint segments, bit for bit (FP64)."""
+    cfg = W.melting_cavity(10, 1e5, 0.5, 0.2, precision=W.FP64)
+    cfg.update(ny=8, nz=7)
+    walls = {0: W.hot_wall_field(8, 7)}
+    out = []
+    for every in (7, 1):
+        cav = make_cavity(cfg, walls=walls)
+        L = cav.adjoint_forward(45, every)
+        dtw, dt0 = cav.adjoint_backward(want_T0=True)
+        f, g = cav.state()
+        out.append((L, dtw.cpu().numpy(), dt0.cpu().numpy(), g.cpu().numpy(), cav.budgets()[0, 4]))
+    (L7, d7, t7, g7, s7), (L1, d1, t1, g1, s1) = out
+    assert L1 == L7 and s1 == s7 == 45
+    assert np.array_equal(g1, g7)
+    assert np.array_equal(d1, d7) and np.array_equal(t1, t7)
+    assert np.abs(d1).max() > 1e-3
