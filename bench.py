@@ -73,7 +73,7 @@ def run_cavity(cfg, steps, warmup, launch=None, label=""):
                      launch=list(cav.get_launch()), unstable=int(st.max()))
 
 
-def precision_errors(n=256, steps=1000):
+def precision_errors(n=256, steps=5000):
     """Shifted FP16 / BF16 storage against the FP32 GPU run of the same cavity
     (Ra 1e6, Pr 0.02 and 6.2): max and RMS errors of T, |u| and f_l, and the
     difference of the mean liquid fraction."""
@@ -126,6 +126,56 @@ def cpu_baseline(cfg, target_s=12.0, max_steps=400):
     return dict(value=cells * n / dt / 1e6, unit="MLUPS", cores=oracle.threads(), kind="oracle",
                 sample=f"{cfg['nx']}x{cfg['ny']}x{cfg['nz']} coupled FP64 oracle, {n} steps "
                        f"from the same initial state ({dt:.1f} s)")
+
+
+def cpu_scaled():
+    """The oracle on the scaled configurations: the 64^3 coupled cavity and the
+    1D melting case (64 x 4 x 4, 2000 steps, MRT) in full, on all host cores and
+    on one core."""
+    import oracle
+    import workloads as W
+    out = {}
+    n_all = oracle.threads()
+    try:
+        for threads in (n_all, 1):
+            oracle.set_threads(threads)
+            cfg = W.melting_cavity(64, 1e5, 0.02, 0.1, precision=W.FP64)
+            st = oracle.run(cfg, oracle.init_state(cfg), 1)
+            steps = 40 if threads > 1 else 8
+            t = time.perf_counter()
+            oracle.run(cfg, st, steps)
+            dt = time.perf_counter() - t
+            out[f"cavity64_coupled_{threads}threads"] = dict(
+                mlups=64**3 * steps / dt / 1e6, steps=steps, seconds=round(dt, 3))
+            c1 = W.stefan_1d(W.MRT)
+            t = time.perf_counter()
+            oracle.run(c1, oracle.init_state(c1), 2000)
+            dt = time.perf_counter() - t
+            out[f"melting1d_2000steps_{threads}threads"] = dict(
+                mlups=64 * 16 * 2000 / dt / 1e6, seconds=round(dt, 3))
+    finally:
+        oracle.set_threads(n_all)
+    return out
+
+
+def full_run_128(launch, steps=20000):
+    """The 128^3 cavity over its whole run (Fo = 0.2) in one timed call, with the
+    liquid fraction and the hot-wall Nusselt number at the end."""
+    import torch
+    import workloads as W
+    from paper_1703_02652_amd import Cavity
+    cfg = W.cavity_128(precision=W.FP32)
+    cav = Cavity(cfg, device="cuda")
+    cav.set_launch(*launch)
+    dt = timed_steps(cav, steps)
+    b = cav.budgets()
+    r = dict(steps=steps, seconds=round(dt, 3), mlups=128**3 * steps / dt / 1e6,
+             mean_fl=round(float(b[0, 2]) / 128**3, 6), nusselt_hot_wall=round(float(cav.nusselt(b=b)), 4),
+             unstable=int(cav.status().max()))
+    cav.close()
+    del cav
+    torch.cuda.empty_cache()
+    return r
 
 
 def adjoint_ratio(prec, n=96, steps=200, every=100):
@@ -305,6 +355,8 @@ def main():
         log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
         extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)
         log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
+        extras["cavity128_full_run_fp32"] = full_run_128(main_r["launch"])
+        log(f"[bench] 128^3 full run: {extras['cavity128_full_run_fp32']}")
         extras["adjoint96_fp32_every_step"] = adjoint_ratio(W.FP32, every=1)
         log(f"[bench] adjoint fp32, a snapshot per step: {extras['adjoint96_fp32_every_step']}")
         extras.update(two_d_validations())
@@ -314,6 +366,9 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(dict(cfg, precision=W.FP64))
         log(f"[bench] cpu baseline: {cpu}")
+        if not args.no_extras:
+            extras["cpu_oracle_scaled"] = cpu_scaled()
+            log(f"[bench] cpu scaled: {extras['cpu_oracle_scaled']}")
 
     out = dict(
         metric=f"coupled flow+enthalpy MLUPS ({args.workload})",

@@ -164,10 +164,11 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
  * best average step-kernel time in milliseconds.  Synchronises the stream. */
 int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 
-/* Advance nsteps with eager step-kernel launches whose start and end events
- * are recorded by the dispatch itself (hipExtLaunchKernel), on the library's
- * stream; the mean kernel time in milliseconds goes to host_ms_out.
- * Synchronises. */
+/* Advance nsteps with eager step-kernel launches on the library's stream:
+ * runs of up to 15 back-to-back wall-inflow-partials steps (the kernel the
+ * graphs run) between one HIP event pair each, then one step with all
+ * partials outside the timed window.  The mean time per timed step in
+ * milliseconds goes to host_ms_out.  Synchronises. */
 int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
 
 /* Discrete adjoint of the loss L = sum over cells of f_l at the final step

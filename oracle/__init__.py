@@ -62,6 +62,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P = _c_double_p
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_tables.argtypes = [P] * 6
         L.or_g_eq.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, P, P]
@@ -91,6 +92,11 @@ def _p(a):
 
 def threads() -> int:
     return lib().or_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (for timing)."""
+    lib().or_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------- #

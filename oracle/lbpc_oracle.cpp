@@ -579,6 +579,15 @@ int or_threads() {
 #endif
 }
 
+// Threads for the following runs (timing on one core against all cores).
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void or_tables(double* e7, double* e19, double* n7, double* n7inv, double* m19,
                double* m19inv) {
   build_tables();

@@ -439,7 +439,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum NPART values over the workgroup in a fixed order and store them (thread 0).
+// Sum NPART values over the workgroup in a fixed order and store them (thread 0);
+// v is reduced in place.
 __device__ __forceinline__ void block_partials(double* v, double* out, double (*red)[NPART]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -460,28 +461,19 @@ __device__ __forceinline__ void block_partials(double* v, double* out, double (*
   __syncthreads();
 }
 
-// Wall inflow only: one double per tile (the other partials are written as 0).
-// Tiles without a nonzero inflow skip the reduction.
-__device__ __forceinline__ void block_flux(double v, double* out, double (*red)[NPART]) {
-  if (!__syncthreads_or(v != 0.0)) {
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int k = 0; k < NPART; ++k) out[k] = 0.0;
+// Wall inflow of one wavefront, stored by its first lane in the tile record
+// (no workgroup barrier: the waves of a tile retire independently, without
+// waiting for each other's population stores).  Wave 0 also clears the
+// entries of waves that a smaller tile does not have.
+__device__ __forceinline__ void wave_flux(double v, double* rec) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = __any(v != 0.0) ? wave_sum(v) : 0.0;
+  if (lane == 0) {
+    rec[NPART + wave] = v;
+    if (wave == 0) {
+      for (int w = static_cast<int>(blockDim.x >> 6); w < NWAVE; ++w) rec[NPART + w] = 0.0;
     }
-    return;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_sum(v);
-  if (lane == 0) red[wave][0] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += red[w][0];
-#pragma unroll
-    for (int k = 0; k < NPART; ++k) out[k] = 0.0;
-    out[3] = s;
-  }
-  __syncthreads();
 }
 
 // Tiles handled by this workgroup.  With xcd > 1 (a grid that is a multiple of
@@ -651,8 +643,9 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         acc[4] = bad ? 1.0 : 0.0;
       }
     }
-    if (BUDGET == 2) block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
-    if (BUDGET == 1) block_flux(acc[3], partials + static_cast<int64_t>(t) * NPART, red);
+    // the wave's own inflow first: block_partials reduces acc in place
+    if (BUDGET >= 1) wave_flux(acc[3], partials + static_cast<int64_t>(t) * TREC);
+    if (BUDGET == 2) block_partials(acc, partials + static_cast<int64_t>(t) * TREC, red);
   }
 }
 
@@ -741,7 +734,7 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
       acc[2] = fl;
       acc[4] = isfinite(h) && isfinite(rho) ? 0.0 : 1.0;
     }
-    block_partials(acc, partials + static_cast<int64_t>(t) * NPART, red);
+    block_partials(acc, partials + static_cast<int64_t>(t) * TREC, red);
   }
 }
 
