@@ -62,12 +62,11 @@ struct alignas(16) BudgetRec {
   double pad[2];
 };
 
-constexpr int NPART = 5;        // per-tile partials: h, rho, f_l, wall flux, bad cells
-constexpr int NWAVE = 4;        // wavefronts of the largest tile (256 cells)
-// Per-tile record in a partials slot: [0, NPART) the workgroup sums (written by
-// full-partials steps and the measure pass), then one wall-inflow value per
-// wavefront (written by every step with partials, without a workgroup barrier).
-constexpr int TREC = NPART + NWAVE;
+// Partials are written per wavefront (64 cells), NPART doubles each: h, rho,
+// f_l, wall inflow, bad cells.  Steps with inflow partials only write the
+// inflow; full-partials steps and the measure pass write all five.  No
+// workgroup barrier is involved: the waves of a tile retire independently.
+constexpr int NPART = 5;
 
 struct StepArgs {
   const CavParams* cavs;
@@ -75,7 +74,7 @@ struct StepArgs {
   int ntiles;
   const char* src;              // state region read (pre-collision state at t)
   char* dst;                    // state region written (pre-collision state at t+1)
-  double* partials;             // TREC doubles per tile (unused when budget = 0)
+  double* partials;             // NPART doubles per wavefront (unused when budget = 0)
   const int32_t* status;        // per-cavity freeze flags
   int budget;                   // 0 none, 1 wall inflow only, 2 all partials
   int block, grid;              // grid = 0: one workgroup per tile

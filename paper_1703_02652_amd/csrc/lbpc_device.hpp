@@ -439,40 +439,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum NPART values over the workgroup in a fixed order and store them (thread 0);
-// v is reduced in place.
-__device__ __forceinline__ void block_partials(double* v, double* out, double (*red)[NPART]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NPART; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NPART; ++k) red[wave][k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NPART; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < nw; ++w) s += red[w][k];
-      out[k] = s;
-    }
-  }
-  __syncthreads();
-}
-
-// Wall inflow of one wavefront, stored by its first lane in the tile record
-// (no workgroup barrier: the waves of a tile retire independently, without
-// waiting for each other's population stores).  Wave 0 also clears the
-// entries of waves that a smaller tile does not have.
-__device__ __forceinline__ void wave_flux(double v, double* rec) {
+// Partials of one wavefront: the wave sums of v[0..NPART) (ALL) or of the wall
+// inflow v[3] alone, stored by the first lane in the wave's record (global
+// wave index = tile * waves per tile + wave).  No workgroup barrier: the waves
+// of a tile retire without waiting for each other's population stores.
+template <bool ALL>
+__device__ __forceinline__ void wave_partials(const double* v, double* partials, int tile) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = __any(v != 0.0) ? wave_sum(v) : 0.0;
-  if (lane == 0) {
-    rec[NPART + wave] = v;
-    if (wave == 0) {
-      for (int w = static_cast<int>(blockDim.x >> 6); w < NWAVE; ++w) rec[NPART + w] = 0.0;
+  double* rec = partials + (static_cast<int64_t>(tile) * (blockDim.x >> 6) + wave) * NPART;
+  if (ALL) {
+    double s[NPART];
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) s[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) rec[k] = s[k];
     }
+  } else {
+    const double f = __any(v[3] != 0.0) ? wave_sum(v[3]) : 0.0;
+    if (lane == 0) rec[3] = f;
   }
 }
 
@@ -512,7 +497,6 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
   using R = typename Fmt<P>::R;
-  __shared__ double red[4][NPART];
   for (TileIter it = tile_iter(ntiles, xcd); it.t < it.end; it.t += it.stride) {
     const int t = it.t;
     const int2 tl = tiles[t];
@@ -643,9 +627,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         acc[4] = bad ? 1.0 : 0.0;
       }
     }
-    // the wave's own inflow first: block_partials reduces acc in place
-    if (BUDGET >= 1) wave_flux(acc[3], partials + static_cast<int64_t>(t) * TREC);
-    if (BUDGET == 2) block_partials(acc, partials + static_cast<int64_t>(t) * TREC, red);
+    if (BUDGET == 2) wave_partials<true>(acc, partials, t);
+    if (BUDGET == 1) wave_partials<false>(acc, partials, t);
   }
 }
 
@@ -687,7 +670,6 @@ __global__ void __launch_bounds__(256)
 k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
           const char* __restrict__ src, double* __restrict__ partials) {
   using R = typename Fmt<P>::R;
-  __shared__ double red[4][NPART];
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int2 tl = tiles[t];
     const CavParams& c = cavs[tl.x];
@@ -734,7 +716,7 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
       acc[2] = fl;
       acc[4] = isfinite(h) && isfinite(rho) ? 0.0 : 1.0;
     }
-    block_partials(acc, partials + static_cast<int64_t>(t) * TREC, red);
+    wave_partials<true>(acc, partials, t);
   }
 }
 

@@ -34,29 +34,23 @@ thread_local std::string g_err;
 // ---------------------------------------------------------------------------
 // Kernels that do not depend on the storage format
 // ---------------------------------------------------------------------------
-// Budget reduction, pass 1: one workgroup per (chunk, slot) sums the tile
-// records of a run of at most kChunk tiles of one cavity in a fixed order.
-// mode 0 (steps): the wall inflow is the sum of the per-wavefront entries;
-// mode 1 (measure pass): every quantity comes from the workgroup sums.
+// Budget reduction, pass 1: one workgroup per (chunk, slot) sums the wavefront
+// records of a run of at most kChunk tiles of one cavity in a fixed order
+// (wpt wavefronts per tile).  The wall inflow is written by every step with
+// partials; the other sums only by full-partials steps and the measure pass,
+// and only the last slot of a reduction uses them.
 __global__ void __launch_bounds__(256)
 k_reduce_chunks(const int4* __restrict__ chunks, const double* __restrict__ partials,
-                int64_t slot_stride, double* __restrict__ csum, int64_t csum_stride, int mode) {
+                int64_t slot_stride, double* __restrict__ csum, int64_t csum_stride, int wpt) {
   __shared__ double sh[256][NPART];
   const int4 ch = chunks[blockIdx.x];  // (cavity, first tile, end tile, -)
   const double* p = partials + static_cast<int64_t>(blockIdx.y) * slot_stride;
   double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t = ch.y + static_cast<int>(threadIdx.x); t < ch.z; t += blockDim.x) {
-    const double* rec = p + static_cast<int64_t>(t) * TREC;
-    v[0] += rec[0];   // state sums and bad cells: only meaningful in the last slot
-    v[1] += rec[1];
-    v[2] += rec[2];
-    v[4] += rec[4];
-    if (mode == 0) {  // flux-only slots never write rec[3]
+  const int w0 = ch.y * wpt, w1 = ch.z * wpt;
+  for (int w = w0 + static_cast<int>(threadIdx.x); w < w1; w += blockDim.x) {
+    const double* rec = p + static_cast<int64_t>(w) * NPART;
 #pragma unroll
-      for (int w = 0; w < NWAVE; ++w) v[3] += rec[NPART + w];
-    } else {
-      v[3] += rec[3];
-    }
+    for (int k = 0; k < NPART; ++k) v[k] += rec[k];
   }
 #pragma unroll
   for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] = v[k];
@@ -79,47 +73,55 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// Pass 2: one wavefront per cavity folds its chunk sums slot by slot, in slot
-// order.  mode 0 (steps): the wall inflow of every slot is accumulated and the
-// other sums are those of the last slot (the step that wrote full partials);
-// mode 1 (measure of the current state): sums go to the now_* fields.
-__global__ void __launch_bounds__(64)
+// Pass 2: one workgroup per cavity; wavefront s sums the chunk sums of slot s
+// (the same per-lane order as a single wavefront walking the slots), then one
+// thread folds the slots in slot order.  mode 0 (steps): the wall inflow of
+// every slot accumulates and the other sums are those of the last slot (the
+// step that wrote full partials); mode 1 (measure of the current state): sums
+// go to the now_* fields.
+__global__ void __launch_bounds__(64 * kRing)
 k_reduce_final(const CavParams* __restrict__ cavs, const double* __restrict__ csum,
                int64_t csum_stride, int nslots, int mode, BudgetRec* __restrict__ rec,
                int32_t* __restrict__ status) {
+  __shared__ double tot[kRing][NPART];
   const CavParams& c = cavs[blockIdx.x];
   BudgetRec& r = rec[blockIdx.x];
-  // the wall inflow of every slot accumulates; the state sums and the bad-cell
-  // count come from the last slot (a full-partials step or the measure pass)
-  double cum = r.flux_cum, last[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < nslots; ++s) {
+  const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
+  if (s < nslots) {
     double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int j = threadIdx.x; j < c.nchunks; j += 64) {
+    for (int j = lane; j < c.nchunks; j += 64) {
 #pragma unroll
       for (int k = 0; k < NPART; ++k)
         v[k] += csum[static_cast<int64_t>(s) * csum_stride + static_cast<int64_t>(c.chunk0 + j) * NPART + k];
     }
 #pragma unroll
-    for (int k = 0; k < NPART; ++k) last[k] = wave_total(v[k]);
-    cum += last[3];
-  }
-  const double bad = last[4];
-  if (threadIdx.x == 0) {
-    if (mode == 0) {
-      r.H = last[0];
-      r.mass = last[1];
-      r.fl = last[2];
-      r.flux_last = last[3];
-      r.flux_cum = cum;
-      r.steps += nslots;
-    } else {
-      r.now_H = last[0];
-      r.now_mass = last[1];
-      r.now_fl = last[2];
-      r.now_flux0 = last[3];
+    for (int k = 0; k < NPART; ++k) v[k] = wave_total(v[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) tot[s][k] = v[k];
     }
-    if (bad > 0.0 || !isfinite(last[0]) || !isfinite(last[1]) || !isfinite(cum)) status[blockIdx.x] = 1;
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double cum = r.flux_cum, last[NPART];
+  for (int t = 0; t < nslots; ++t) cum += tot[t][3];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) last[k] = tot[nslots - 1][k];
+  if (mode == 0) {
+    r.H = last[0];
+    r.mass = last[1];
+    r.fl = last[2];
+    r.flux_last = last[3];
+    r.flux_cum = cum;
+    r.steps += nslots;
+  } else {
+    r.now_H = last[0];
+    r.now_mass = last[1];
+    r.now_fl = last[2];
+    r.now_flux0 = last[3];
+  }
+  if (last[4] > 0.0 || !isfinite(last[0]) || !isfinite(last[1]) || !isfinite(cum))
+    status[blockIdx.x] = 1;
 }
 
 __global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t nwords) {
@@ -135,7 +137,8 @@ struct Layout {
   int batch = 0, prec = 0, flow = 0, mrt = 0;
   std::vector<int64_t> ncell, off, plane, cell_off, tw_off;
   std::vector<std::array<int64_t, 6>> twface;
-  int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, max_chunks = 0, tw_doubles = 0;
+  int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, max_waves = 0, max_chunks = 0,
+          tw_doubles = 0;
   size_t o_params = 0, o_tiles = 0, o_chunks = 0, o_csum = 0, o_tw = 0, o_status = 0, o_rec = 0,
          o_part = 0, o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
 };
@@ -214,7 +217,7 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.flow = cfgs[0].flow;
   L.mrt = cfgs[0].enth_model;
   const size_t pb = pop_bytes(L.prec), g0b = g0_bytes(L.prec);
-  int64_t off = 0, cells = 0, tiles = 0, chunks = 0, tw = 0;
+  int64_t off = 0, cells = 0, tiles = 0, chunks = 0, tw = 0, waves = 0;
   for (int i = 0; i < batch; ++i) {
     const lbpc_config& c = cfgs[i];
     const int64_t n = static_cast<int64_t>(c.nx) * c.ny * c.nz;
@@ -230,6 +233,7 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
     const int64_t ct = (n + kMinTile - 1) / kMinTile;
     tiles += ct;
     chunks += (ct + kChunk - 1) / kChunk;
+    waves += (n + kMaxTile - 1) / kMaxTile * (kMaxTile / 64);  // any tile size
     std::array<int64_t, 6> tf;
     int64_t fo = 0;
     for (int f = 0; f < 6; ++f) {
@@ -243,6 +247,7 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.region_bytes = off;
   L.total_cells = cells;
   L.max_tiles = tiles;
+  L.max_waves = waves;
   L.max_chunks = chunks;
   L.tw_doubles = tw;
   size_t o = 0;
@@ -253,8 +258,8 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.o_tw = o; o = align_up(o + sizeof(double) * tw);
   L.o_status = o; o = align_up(o + sizeof(int32_t) * batch);
   L.o_rec = o; o = align_up(o + sizeof(BudgetRec) * batch);
-  L.o_part = o; o = align_up(o + sizeof(double) * TREC * tiles * kRing);
-  L.o_mpart = o; o = align_up(o + sizeof(double) * TREC * tiles);
+  L.o_part = o; o = align_up(o + sizeof(double) * NPART * waves * kRing);
+  L.o_mpart = o; o = align_up(o + sizeof(double) * NPART * waves);
   L.o_region0 = o; o = align_up(o + L.region_bytes);
   L.o_region1 = o; o = align_up(o + L.region_bytes);
   L.total = o;
@@ -455,9 +460,9 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
 hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st) {
   const int64_t csum_stride = x->L.max_chunks * NPART;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(x->nchunks, nslots), dim3(256), 0, st, x->d_chunks,
-                     partials, static_cast<int64_t>(x->L.max_tiles) * TREC, x->d_csum, csum_stride,
-                     mode);
-  hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64), 0, st, x->d_params, x->d_csum,
+                     partials, static_cast<int64_t>(x->L.max_waves) * NPART, x->d_csum, csum_stride,
+                     x->block / 64);
+  hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64 * nslots), 0, st, x->d_params, x->d_csum,
                      csum_stride, nslots, mode, x->d_rec, x->d_status);
   return hipGetLastError();
 }
@@ -509,7 +514,7 @@ int flush(lbpc_ctx* x) {
 
 // One eager step: partials into the next ring slot, reduction when the ring fills.
 int eager_step(lbpc_ctx* x) {
-  double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * TREC;
+  double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
   HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, 2, x->stream));
   x->cur ^= 1;
   x->steps += 1;
@@ -523,7 +528,7 @@ int capture(lbpc_ctx* x, int from) {
   int c = from;
   hipError_t e = hipSuccess;
   for (int i = 0; i < x->graph_steps && e == hipSuccess; ++i) {
-    double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_tiles * TREC;
+    double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_waves * NPART;
     e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, i + 1 == x->graph_steps ? 2 : 1,
                       x->cap);
     c ^= 1;
@@ -875,7 +880,7 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   HIPCHK(x, hipEventCreate(&e0));
   HIPCHK(x, hipEventCreate(&e1));
   auto one_step = [&](int budget) -> hipError_t {
-    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * TREC;
+    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
     const hipError_t e =
         dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget, x->stream);
     x->cur ^= 1;
@@ -1034,7 +1039,7 @@ int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t los
     HIPCHK(x, hipMemcpyAsync(snap, x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
     for (int64_t t = 0; t < nsteps; ++t) {
       char* dst = t + 1 < nsteps ? snap + rb * static_cast<size_t>(t + 1) : x->region[x->cur ^ 1];
-      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_tiles * TREC;
+      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
       // all partials only where a reduction closes (as the graphs do)
       const int budget = (x->pending + 1 == kRing || t + 1 == nsteps) ? 2 : 1;
       HIPCHK(x, dispatch_step(x, snap + rb * static_cast<size_t>(t), dst, part, budget, x->stream));
