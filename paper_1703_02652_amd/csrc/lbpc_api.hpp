@@ -62,10 +62,12 @@ struct alignas(16) BudgetRec {
   double pad[2];
 };
 
-// Partials are written per wavefront (64 cells), NPART doubles each: h, rho,
-// f_l, wall inflow, bad cells.  Steps with inflow partials only write the
-// inflow; full-partials steps and the measure pass write all five.  No
-// workgroup barrier is involved: the waves of a tile retire independently.
+// Budget partials are written per wavefront (64 cells), without a workgroup
+// barrier, so the waves of a tile retire independently.  Every step with
+// partials writes its wall inflow into a dense per-wavefront array of its ring
+// slot; full-partials steps also write the NPART state sums (h, rho, f_l,
+// inflow, bad cells) of the wave into one shared record array, of which a
+// reduction uses the last.  The measure pass writes the same records.
 constexpr int NPART = 5;
 
 struct StepArgs {
@@ -74,15 +76,14 @@ struct StepArgs {
   int ntiles;
   const char* src;              // state region read (pre-collision state at t)
   char* dst;                    // state region written (pre-collision state at t+1)
-  double* partials;             // NPART doubles per wavefront (unused when budget = 0)
+  double* partials;             // wall inflow, one double per wavefront (budget >= 1)
+  double* sums;                 // NPART doubles per wavefront (budget 2)
   const int32_t* status;        // per-cavity freeze flags
   int budget;                   // 0 none, 1 wall inflow only, 2 all partials
   int block, grid;              // grid = 0: one workgroup per tile
   int xcd;                      // > 1: XCD-contiguous tile order (grid rounded up)
   int flow, mrt;
   hipStream_t stream;
-  hipEvent_t ev_start = nullptr;  // non-null: the dispatch itself records start and end
-  hipEvent_t ev_stop = nullptr;
 };
 
 struct AdjArgs {

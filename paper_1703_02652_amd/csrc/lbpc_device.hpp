@@ -439,25 +439,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Partials of one wavefront: the wave sums of v[0..NPART) (ALL) or of the wall
-// inflow v[3] alone, stored by the first lane in the wave's record (global
-// wave index = tile * waves per tile + wave).  No workgroup barrier: the waves
-// of a tile retire without waiting for each other's population stores.
-template <bool ALL>
-__device__ __forceinline__ void wave_partials(const double* v, double* partials, int tile) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* rec = partials + (static_cast<int64_t>(tile) * (blockDim.x >> 6) + wave) * NPART;
-  if (ALL) {
-    double s[NPART];
+// Budget partials of one wavefront (global wave index = tile * waves per tile
+// + wave), stored by its first lane; no workgroup barrier, so the waves of a
+// tile retire without waiting for each other's population stores.
+__device__ __forceinline__ int64_t wave_index(int tile) {
+  return static_cast<int64_t>(tile) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+}
+// wall inflow into the dense per-wavefront array of a ring slot
+__device__ __forceinline__ void wave_inflow(double v, double* flux, int tile) {
+  const double f = __any(v != 0.0) ? wave_sum(v) : 0.0;
+  if ((threadIdx.x & 63) == 0) flux[wave_index(tile)] = f;
+}
+// the NPART sums of v into the wave's record (and the inflow sum into the
+// slot's array when flux is given)
+__device__ __forceinline__ void wave_sums(const double* v, double* sums, int tile,
+                                          double* flux = nullptr) {
+  double s[NPART];
 #pragma unroll
-    for (int k = 0; k < NPART; ++k) s[k] = wave_sum(v[k]);
-    if (lane == 0) {
+  for (int k = 0; k < NPART; ++k) s[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63) == 0) {
+    const int64_t w = wave_index(tile);
+    double* rec = sums + w * NPART;
 #pragma unroll
-      for (int k = 0; k < NPART; ++k) rec[k] = s[k];
-    }
-  } else {
-    const double f = __any(v[3] != 0.0) ? wave_sum(v[3]) : 0.0;
-    if (lane == 0) rec[3] = f;
+    for (int k = 0; k < NPART; ++k) rec[k] = s[k];
+    if (flux) flux[w] = s[3];
   }
 }
 
@@ -493,7 +498,7 @@ template <int P, bool FLOW, bool MRT, int BUDGET>
 __global__ void __launch_bounds__(256)
 k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int xcd,
        const char* __restrict__ src, char* __restrict__ dst, double* __restrict__ partials,
-       const int32_t* __restrict__ status) {
+       double* __restrict__ sums, const int32_t* __restrict__ status) {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
   using R = typename Fmt<P>::R;
@@ -627,8 +632,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         acc[4] = bad ? 1.0 : 0.0;
       }
     }
-    if (BUDGET == 2) wave_partials<true>(acc, partials, t);
-    if (BUDGET == 1) wave_partials<false>(acc, partials, t);
+    if (BUDGET == 1) wave_inflow(acc[3], partials, t);
+    if (BUDGET == 2) wave_sums(acc, sums, t, partials);
   }
 }
 
@@ -716,7 +721,7 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
       acc[2] = fl;
       acc[4] = isfinite(h) && isfinite(rho) ? 0.0 : 1.0;
     }
-    wave_partials<true>(acc, partials, t);
+    wave_sums(acc, partials, t);
   }
 }
 

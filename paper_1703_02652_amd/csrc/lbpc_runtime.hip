@@ -35,22 +35,30 @@ thread_local std::string g_err;
 // Kernels that do not depend on the storage format
 // ---------------------------------------------------------------------------
 // Budget reduction, pass 1: one workgroup per (chunk, slot) sums the wavefront
-// records of a run of at most kChunk tiles of one cavity in a fixed order
-// (wpt wavefronts per tile).  The wall inflow is written by every step with
-// partials; the other sums only by full-partials steps and the measure pass,
-// and only the last slot of a reduction uses them.
+// partials of a run of at most kChunk tiles of one cavity in a fixed order
+// (wpt wavefronts per tile).  Steps (flux != null): the wall inflow of slot s
+// from its dense array, the other sums from the shared records, for the last
+// slot only (the step that wrote them).  Measure pass (flux == null): all
+// NPART sums from the records.
 __global__ void __launch_bounds__(256)
-k_reduce_chunks(const int4* __restrict__ chunks, const double* __restrict__ partials,
-                int64_t slot_stride, double* __restrict__ csum, int64_t csum_stride, int wpt) {
+k_reduce_chunks(const int4* __restrict__ chunks, const double* __restrict__ flux,
+                int64_t flux_stride, const double* __restrict__ sums, double* __restrict__ csum,
+                int64_t csum_stride, int wpt) {
   __shared__ double sh[256][NPART];
   const int4 ch = chunks[blockIdx.x];  // (cavity, first tile, end tile, -)
-  const double* p = partials + static_cast<int64_t>(blockIdx.y) * slot_stride;
+  const bool last = blockIdx.y + 1 == gridDim.y;
   double v[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int w0 = ch.y * wpt, w1 = ch.z * wpt;
   for (int w = w0 + static_cast<int>(threadIdx.x); w < w1; w += blockDim.x) {
-    const double* rec = p + static_cast<int64_t>(w) * NPART;
-#pragma unroll
-    for (int k = 0; k < NPART; ++k) v[k] += rec[k];
+    if (flux) v[3] += flux[static_cast<int64_t>(blockIdx.y) * flux_stride + w];
+    if (last) {
+      const double* rec = sums + static_cast<int64_t>(w) * NPART;
+      v[0] += rec[0];
+      v[1] += rec[1];
+      v[2] += rec[2];
+      v[4] += rec[4];
+      if (!flux) v[3] += rec[3];
+    }
   }
 #pragma unroll
   for (int k = 0; k < NPART; ++k) sh[threadIdx.x][k] = v[k];
@@ -140,7 +148,7 @@ struct Layout {
   int64_t region_bytes = 0, total_cells = 0, max_tiles = 0, max_waves = 0, max_chunks = 0,
           tw_doubles = 0;
   size_t o_params = 0, o_tiles = 0, o_chunks = 0, o_csum = 0, o_tw = 0, o_status = 0, o_rec = 0,
-         o_part = 0, o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
+         o_part = 0, o_sums = 0, o_mpart = 0, o_region0 = 0, o_region1 = 0, total = 0;
 };
 
 size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
@@ -258,7 +266,8 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
   L.o_tw = o; o = align_up(o + sizeof(double) * tw);
   L.o_status = o; o = align_up(o + sizeof(int32_t) * batch);
   L.o_rec = o; o = align_up(o + sizeof(BudgetRec) * batch);
-  L.o_part = o; o = align_up(o + sizeof(double) * NPART * waves * kRing);
+  L.o_part = o; o = align_up(o + sizeof(double) * waves * kRing);
+  L.o_sums = o; o = align_up(o + sizeof(double) * NPART * waves);
   L.o_mpart = o; o = align_up(o + sizeof(double) * NPART * waves);
   L.o_region0 = o; o = align_up(o + L.region_bytes);
   L.o_region1 = o; o = align_up(o + L.region_bytes);
@@ -381,8 +390,9 @@ struct lbpc_ctx {
   double* d_tw = nullptr;
   int32_t* d_status = nullptr;
   BudgetRec* d_rec = nullptr;
-  double* d_part = nullptr;
-  double* d_mpart = nullptr;
+  double* d_part = nullptr;   // wall inflow per wavefront, one array per ring slot
+  double* d_sums = nullptr;   // state sums per wavefront (full-partials steps)
+  double* d_mpart = nullptr;  // measure pass records
   char* region[2] = {nullptr, nullptr};
   int cur = 0;
   int block = 256, grid = 0, graph_steps = 16, xcd = kXcd;
@@ -412,11 +422,9 @@ int fail(lbpc_ctx* x, int code, const std::string& msg) {
   } while (0)
 
 hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials, int budget,
-                         hipStream_t st, hipEvent_t ev_start = nullptr,
-                         hipEvent_t ev_stop = nullptr) {
+                         hipStream_t st) {
   StepArgs a;
-  a.ev_start = ev_start;
-  a.ev_stop = ev_stop;
+  a.sums = x->d_sums;
   a.cavs = x->d_params;
   a.tiles = x->d_tiles;
   a.ntiles = x->ntiles;
@@ -457,13 +465,17 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+// mode 0: the steps of the ring (inflow arrays from `partials`, state sums of
+// the last one); mode 1: the measure pass (its records in `partials`).
 hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st) {
   const int64_t csum_stride = x->L.max_chunks * NPART;
+  const double* flux = mode == 0 ? partials : nullptr;
+  const double* sums = mode == 0 ? x->d_sums : partials;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(x->nchunks, nslots), dim3(256), 0, st, x->d_chunks,
-                     partials, static_cast<int64_t>(x->L.max_waves) * NPART, x->d_csum, csum_stride,
+                     flux, static_cast<int64_t>(x->L.max_waves), sums, x->d_csum, csum_stride,
                      x->block / 64);
-  hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64 * nslots), 0, st, x->d_params, x->d_csum,
-                     csum_stride, nslots, mode, x->d_rec, x->d_status);
+  hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64 * nslots), 0, st, x->d_params,
+                     x->d_csum, csum_stride, nslots, mode, x->d_rec, x->d_status);
   return hipGetLastError();
 }
 
@@ -514,7 +526,7 @@ int flush(lbpc_ctx* x) {
 
 // One eager step: partials into the next ring slot, reduction when the ring fills.
 int eager_step(lbpc_ctx* x) {
-  double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
+  double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
   HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, 2, x->stream));
   x->cur ^= 1;
   x->steps += 1;
@@ -528,7 +540,7 @@ int capture(lbpc_ctx* x, int from) {
   int c = from;
   hipError_t e = hipSuccess;
   for (int i = 0; i < x->graph_steps && e == hipSuccess; ++i) {
-    double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_waves * NPART;
+    double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_waves;
     e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, i + 1 == x->graph_steps ? 2 : 1,
                       x->cap);
     c ^= 1;
@@ -627,6 +639,7 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
   x->d_status = reinterpret_cast<int32_t*>(x->ws + L.o_status);
   x->d_rec = reinterpret_cast<BudgetRec*>(x->ws + L.o_rec);
   x->d_part = reinterpret_cast<double*>(x->ws + L.o_part);
+  x->d_sums = reinterpret_cast<double*>(x->ws + L.o_sums);
   x->d_mpart = reinterpret_cast<double*>(x->ws + L.o_mpart);
   x->region[0] = x->ws + L.o_region0;
   x->region[1] = x->ws + L.o_region1;
@@ -880,7 +893,7 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   HIPCHK(x, hipEventCreate(&e0));
   HIPCHK(x, hipEventCreate(&e1));
   auto one_step = [&](int budget) -> hipError_t {
-    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
+    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
     const hipError_t e =
         dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget, x->stream);
     x->cur ^= 1;
@@ -1039,7 +1052,7 @@ int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t los
     HIPCHK(x, hipMemcpyAsync(snap, x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
     for (int64_t t = 0; t < nsteps; ++t) {
       char* dst = t + 1 < nsteps ? snap + rb * static_cast<size_t>(t + 1) : x->region[x->cur ^ 1];
-      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves * NPART;
+      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
       // all partials only where a reduction closes (as the graphs do)
       const int budget = (x->pending + 1 == kRing || t + 1 == nsteps) ? 2 : 1;
       HIPCHK(x, dispatch_step(x, snap + rb * static_cast<size_t>(t), dst, part, budget, x->stream));
