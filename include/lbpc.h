@@ -157,11 +157,12 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
                     int32_t* graph_steps, int32_t* xcd_runs);
 
 /* Time every candidate launch configuration (tile size, persistent grid, XCD
- * order) with real alternating steps from the current state (without budget
- * partials) and keep the
- * fastest.  The state is copied to host memory first and restored afterwards,
- * so tuning does not advance the run.  host_ms_out (nullable) receives the
- * best average step-kernel time in milliseconds.  Synchronises the stream. */
+ * order) with trial_steps real alternating steps from the current state
+ * (without budget partials), re-time the three fastest four times more,
+ * interleaved, and keep the fastest of those.  The state is copied to host
+ * memory first and restored afterwards, so tuning does not advance the run.
+ * host_ms_out (nullable) receives the best average step-kernel time in
+ * milliseconds.  Synchronises the stream. */
 int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 
 /* Advance nsteps with eager step-kernel launches on the library's stream:
