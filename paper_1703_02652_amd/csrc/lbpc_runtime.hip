@@ -577,6 +577,19 @@ int run_steps(lbpc_ctx* x, int64_t n) {
   return LBPC_OK;
 }
 
+// A pair of timing events, destroyed on every exit path.
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t create() {
+    const hipError_t e = hipEventCreate(&e0);
+    return e != hipSuccess ? e : hipEventCreate(&e1);
+  }
+  ~EventPair() {
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  }
+};
+
 int check_cavity(lbpc_ctx* x, int cavity) {
   if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
   if (cavity < 0 || cavity >= x->L.batch) return fail(x, LBPC_EINVAL, "cavity index out of range");
@@ -889,9 +902,9 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   // between one event pair each; the step that closes a reduction carries all
   // partials and runs outside the timed window.  Per-kernel completion events
   // would add their own release to every measured kernel.
-  hipEvent_t e0, e1;
-  HIPCHK(x, hipEventCreate(&e0));
-  HIPCHK(x, hipEventCreate(&e1));
+  EventPair ev;
+  HIPCHK(x, ev.create());
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   auto one_step = [&](int budget) -> hipError_t {
     double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
     const hipError_t e =
@@ -925,8 +938,6 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
     rc = flush(x);
     if (rc) return rc;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   if (host_ms_out) *host_ms_out = counted ? total / static_cast<double>(counted) : single;
   return LBPC_OK;
 }
@@ -951,9 +962,8 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   HIPCHK(x, hipMemcpyAsync(saved.data(), x->region[cur0], saved.size(), hipMemcpyDeviceToHost,
                            x->stream));
   HIPCHK(x, hipStreamSynchronize(x->stream));
-  hipEvent_t e0, e1;
-  HIPCHK(x, hipEventCreate(&e0));
-  HIPCHK(x, hipEventCreate(&e1));
+  EventPair ev;
+  HIPCHK(x, ev.create());
   struct Cand {
     int b, g, xc;
     double ms;
@@ -972,60 +982,66 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
     x->xcd = k.xc;
     for (int i = 0; i < 2; ++i, c ^= 1)
       HIPCHK(x, dispatch_step(x, x->region[c], x->region[c ^ 1], nullptr, 0, x->stream));
-    HIPCHK(x, hipEventRecord(e0, x->stream));
+    HIPCHK(x, hipEventRecord(ev.e0, x->stream));
     for (int i = 0; i < steps; ++i, c ^= 1)
       HIPCHK(x, dispatch_step(x, x->region[c], x->region[c ^ 1], nullptr, 0, x->stream));
-    HIPCHK(x, hipEventRecord(e1, x->stream));
-    HIPCHK(x, hipEventSynchronize(e1));
+    HIPCHK(x, hipEventRecord(ev.e1, x->stream));
+    HIPCHK(x, hipEventSynchronize(ev.e1));
     float ms = 0.f;
-    HIPCHK(x, hipEventElapsedTime(&ms, e0, e1));
+    HIPCHK(x, hipEventElapsedTime(&ms, ev.e0, ev.e1));
     per = ms / steps;
     return LBPC_OK;
   };
   // stage 1: every shape once; stage 2: the three fastest again, interleaved,
   // four rounds each (a drift of the box then hits all three alike)
-  std::vector<Cand> cands;
-  for (int b : blocks) {
-    for (int g : grids)
-    for (int xc : xcds) {
-      x->block = b;  // tile count of this block size decides the grid candidates
-      if (g > 0 && g >= (x->L.total_cells + b - 1) / b) continue;
-      cands.push_back({b, g, xc, 0.0});
+  Cand best{x->block, x->grid, x->xcd, 0.0};
+  auto tune = [&]() -> int {
+    std::vector<Cand> cands;
+    for (int b : blocks)
+      for (int g : grids)
+        for (int xc : xcds) {
+          // a persistent grid must have fewer workgroups than there are tiles
+          if (g > 0 && g >= (x->L.total_cells + b - 1) / b) continue;
+          cands.push_back({b, g, xc, 0.0});
+        }
+    for (Cand& k : cands) {
+      const int r = trial(k, trial_steps, k.ms);
+      if (r) return r;
     }
-  }
-  x->block = -1;
-  for (Cand& k : cands) {
-    rc = trial(k, trial_steps, k.ms);
-    if (rc) return rc;
-  }
-  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
-  const size_t top = std::min<size_t>(3, cands.size());
-  std::vector<double> sum(top, 0.0);
-  for (int round = 0; round < 4; ++round) {
-    for (size_t i = 0; i < top; ++i) {
-      double per = 0.0;
-      rc = trial(cands[i], trial_steps, per);
-      if (rc) return rc;
-      sum[i] += per;
-    }
-  }
-  size_t pick = 0;
-  for (size_t i = 1; i < top; ++i)
-    if (sum[i] < sum[pick]) pick = i;
-  const double best = sum[pick] / 4.0;
-  const int best_b = cands[pick].b, best_g = cands[pick].g, best_x = cands[pick].xc;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  HIPCHK(x, hipMemcpyAsync(x->region[cur0], saved.data(), saved.size(), hipMemcpyHostToDevice,
-                           x->stream));
-  HIPCHK(x, hipStreamSynchronize(x->stream));
+    std::sort(cands.begin(), cands.end(), [](const Cand& p, const Cand& q) { return p.ms < q.ms; });
+    const size_t top = std::min<size_t>(3, cands.size());
+    std::vector<double> sum(top, 0.0);
+    for (int round = 0; round < 4; ++round)
+      for (size_t i = 0; i < top; ++i) {
+        double per = 0.0;
+        const int r = trial(cands[i], trial_steps, per);
+        if (r) return r;
+        sum[i] += per;
+      }
+    size_t pick = 0;
+    for (size_t i = 1; i < top; ++i)
+      if (sum[i] < sum[pick]) pick = i;
+    best = cands[pick];
+    best.ms = sum[pick] / 4.0;
+    return LBPC_OK;
+  };
+  // on failure the previous launch is kept; the state is restored either way
+  const int trc = tune();
+  const std::string terr = x->err;
+  const hipError_t e1 = hipMemcpyAsync(x->region[cur0], saved.data(), saved.size(),
+                                       hipMemcpyHostToDevice, x->stream);
+  const hipError_t e2 = hipStreamSynchronize(x->stream);
   x->cur = cur0;
-  x->block = best_b;
-  x->grid = best_g;
-  x->xcd = best_x;
+  x->block = best.b;
+  x->grid = best.g;
+  x->xcd = best.xc;
   rc = build_tiles(x);
+  if (trc) return fail(x, trc, terr);
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return fail(x, LBPC_EHIP, std::string("restoring the state after tuning: ") +
+                                  hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   if (rc) return rc;
-  if (host_ms_out) *host_ms_out = best;
+  if (host_ms_out) *host_ms_out = best.ms;
   return LBPC_OK;
 }
 
