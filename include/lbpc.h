@@ -147,17 +147,23 @@ int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
 
 /* Launch configuration.  block: threads (and cells) per tile, 64..256, a
  * multiple of 64; grid_blocks: 0 for one workgroup per tile, else a persistent
- * grid that strides over the tile queue; graph_steps: steps per captured HIP
- * graph (even, at most 16, 0 disables graphs); xcd_runs: 1 for plain tile
- * order, k > 1 to split the tile queue into k contiguous runs, one per
- * accelerator complex die (workgroup ids equal modulo k), 8 on MI355X. */
+ * grid (rounded up to a multiple of 8) that strides over the tile queue;
+ * graph_steps: steps per captured HIP graph (even, at most 16, 0 disables
+ * graphs); xcd_run: 1..2^24, the queue order.  The MI355X dispatcher sends
+ * workgroup b to XCD b mod 8; the queue is ordered so that each XCD walks runs
+ * of xcd_run consecutive tiles (in the natural order of the cells), the runs of
+ * the eight XCDs side by side.  1 is the natural order; a run longer than an
+ * eighth of the queue is cut to that length (one contiguous run per XCD).
+ * Results do not depend on any of these settings: the state bit for bit, and
+ * the budgets for a given block size. */
 int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t graph_steps,
-                    int32_t xcd_runs);
+                    int32_t xcd_run);
 int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
-                    int32_t* graph_steps, int32_t* xcd_runs);
+                    int32_t* graph_steps, int32_t* xcd_run);
 
-/* Time every candidate launch configuration (tile size, persistent grid, XCD
- * order) with trial_steps real alternating steps from the current state
+/* Time every candidate launch configuration (tile size 64/128/256, one
+ * workgroup per tile or a persistent grid of 2, 4 or 8 workgroups per compute
+ * unit, XCD runs of 1, 4, 16 tiles or one run per XCD) with trial_steps real alternating steps from the current state
  * (without budget partials), re-time the three fastest four times more,
  * interleaved, and keep the fastest of those.  The state is copied to host
  * memory first and restored afterwards, so tuning does not advance the run.

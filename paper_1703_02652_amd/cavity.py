@@ -179,11 +179,11 @@ class Cavity:
         self._check(self._L.lbpc_load(self._ctx, buf, len(blob)))
 
     # ------------------------------------------------------ launch shapes
-    def set_launch(self, block=256, grid=0, graph_steps=16, xcd_runs=8):
-        self._check(self._L.lbpc_set_launch(self._ctx, block, grid, graph_steps, xcd_runs))
+    def set_launch(self, block=256, grid=0, graph_steps=16, xcd_run=4):
+        self._check(self._L.lbpc_set_launch(self._ctx, block, grid, graph_steps, xcd_run))
 
     def get_launch(self):
-        """(block, grid, graph_steps, xcd_runs)"""
+        """(block, grid, graph_steps, xcd_run)"""
         v = [ctypes.c_int32() for _ in range(4)]
         self._check(self._L.lbpc_get_launch(self._ctx, *[ctypes.byref(a) for a in v]))
         return tuple(a.value for a in v)

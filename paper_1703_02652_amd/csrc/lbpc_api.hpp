@@ -70,6 +70,10 @@ struct alignas(16) BudgetRec {
 // reduction uses the last.  The measure pass writes the same records.
 constexpr int NPART = 5;
 
+// Accelerator complex dies of an MI355X.  The dispatcher hands workgroups to
+// the XCDs round robin: workgroup b runs on XCD b mod kXcds.
+constexpr int kXcds = 8;
+
 struct StepArgs {
   const CavParams* cavs;
   const int2* tiles;            // (cavity, first cell) per tile
@@ -81,7 +85,6 @@ struct StepArgs {
   const int32_t* status;        // per-cavity freeze flags
   int budget;                   // 0 none, 1 wall inflow only, 2 all partials
   int block, grid;              // grid = 0: one workgroup per tile
-  int xcd;                      // > 1: XCD-contiguous tile order (grid rounded up)
   int flow, mrt;
   hipStream_t stream;
 };
@@ -94,7 +97,7 @@ struct AdjArgs {
   const char* lam_in;           // adjoint of the state at t+1 (compute format)
   char* lam_out;                // adjoint of the state at t
   double* dTw;                  // wall-temperature gradient accumulators (per cavity block)
-  int block, xcd;
+  int block;
   int flow, mrt;
   hipStream_t stream;
 };

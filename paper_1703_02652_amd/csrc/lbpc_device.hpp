@@ -440,8 +440,13 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Budget partials of one wavefront (global wave index = tile * waves per tile
-// + wave), stored by its first lane; no workgroup barrier, so the waves of a
-// tile retire without waiting for each other's population stores.
+// + wave, with the tile's place in the natural order of the cavities' cells,
+// whatever the queue order), stored by its first lane; no workgroup barrier,
+// so the waves of a tile retire without waiting for each other's population
+// stores.
+__device__ __forceinline__ int natural_tile(const CavParams& c, int2 tl) {
+  return c.tile0 + tl.y / static_cast<int>(blockDim.x);
+}
 __device__ __forceinline__ int64_t wave_index(int tile) {
   return static_cast<int64_t>(tile) * (blockDim.x >> 6) + (threadIdx.x >> 6);
 }
@@ -466,29 +471,6 @@ __device__ __forceinline__ void wave_sums(const double* v, double* sums, int til
   }
 }
 
-// Tiles handled by this workgroup.  With xcd > 1 (a grid that is a multiple of
-// xcd), the workgroups that the dispatcher sends to one XCD (block ids equal
-// modulo xcd) walk one contiguous run of the tile queue, so that neighbouring
-// tiles, whose links cross into each other, share that XCD's L2.
-struct TileIter {
-  int t, end, stride;
-};
-__device__ __forceinline__ TileIter tile_iter(int ntiles, int xcd) {
-  TileIter it;
-  if (xcd <= 1) {
-    it.t = blockIdx.x;
-    it.end = ntiles;
-    it.stride = gridDim.x;
-    return it;
-  }
-  const int chunk = (ntiles + xcd - 1) / xcd;
-  const int x = blockIdx.x % xcd, k = blockIdx.x / xcd;
-  it.t = x * chunk + k;
-  it.end = min(x * chunk + chunk, ntiles);
-  it.stride = gridDim.x / xcd;
-  return it;
-}
-
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
@@ -496,14 +478,13 @@ __device__ __forceinline__ TileIter tile_iter(int ntiles, int xcd) {
 // 2 all partials (h, rho, f_l, wall inflow, bad cells).
 template <int P, bool FLOW, bool MRT, int BUDGET>
 __global__ void __launch_bounds__(256)
-k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int xcd,
+k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
        const char* __restrict__ src, char* __restrict__ dst, double* __restrict__ partials,
        double* __restrict__ sums, const int32_t* __restrict__ status) {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
   using R = typename Fmt<P>::R;
-  for (TileIter it = tile_iter(ntiles, xcd); it.t < it.end; it.t += it.stride) {
-    const int t = it.t;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int2 tl = tiles[t];
     const CavParams& c = cavs[tl.x];
     const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
@@ -632,8 +613,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         acc[4] = bad ? 1.0 : 0.0;
       }
     }
-    if (BUDGET == 1) wave_inflow(acc[3], partials, t);
-    if (BUDGET == 2) wave_sums(acc, sums, t, partials);
+    if (BUDGET == 1) wave_inflow(acc[3], partials, natural_tile(c, tl));
+    if (BUDGET == 2) wave_sums(acc, sums, natural_tile(c, tl), partials);
   }
 }
 
@@ -721,7 +702,7 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
       acc[2] = fl;
       acc[4] = isfinite(h) && isfinite(rho) ? 0.0 : 1.0;
     }
-    wave_sums(acc, partials, t);
+    wave_sums(acc, partials, natural_tile(c, tl));
   }
 }
 

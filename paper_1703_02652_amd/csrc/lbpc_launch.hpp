@@ -8,22 +8,23 @@ namespace lbpc {
 
 inline dim3 cell_grid(int64_t n) { return dim3(static_cast<unsigned>((n + 255) / 256)); }
 
-// Workgroups for ntiles tiles: one per tile, or a persistent grid; with an
-// XCD-contiguous order the count is a multiple of xcd.
-inline int step_grid(int ntiles, int grid, int xcd) {
-  int g = grid > 0 ? (grid < ntiles ? grid : ntiles) : ntiles;
-  if (xcd > 1) g = (g + xcd - 1) / xcd * xcd;
-  return g;
+// Workgroups for ntiles tiles: one per tile, or a persistent grid rounded up to
+// a multiple of kXcds (workgroup b then keeps to queue positions equal to b
+// modulo kXcds, which the dispatcher sends to one XCD).
+inline int step_grid(int ntiles, int grid) {
+  if (grid <= 0) return ntiles;
+  const int g = grid < ntiles ? grid : ntiles;
+  return (g + kXcds - 1) / kXcds * kXcds;
 }
 
 template <int P>
 hipError_t launch_step(const StepArgs& a) {
   if (a.ntiles <= 0) return hipSuccess;
-  const dim3 grid(step_grid(a.ntiles, a.grid, a.xcd));
+  const dim3 grid(step_grid(a.ntiles, a.grid));
   const dim3 block(a.block);
 #define LBPC_STEP(FL, MR, BU)                                                              \
   hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
-                     a.ntiles, a.xcd, a.src, a.dst, a.partials, a.sums, a.status)
+                     a.ntiles, a.src, a.dst, a.partials, a.sums, a.status)
 #define LBPC_STEP_B(FL, MR)                                    \
   do {                                                         \
     if (a.budget == 2) LBPC_STEP(FL, MR, 2);                   \
@@ -88,10 +89,10 @@ hipError_t launch_set_state(const CavParams* cav, int64_t n, int flow, char* dst
 
 template <int P>
 hipError_t launch_adjoint(const AdjArgs& a) {
-  const dim3 grid(step_grid(a.ntiles, 0, a.xcd)), block(a.block);
+  const dim3 grid(step_grid(a.ntiles, 0)), block(a.block);
 #define LBPC_ADJ(FL, MR)                                                                    \
   hipLaunchKernelGGL((k_adjoint<P, FL, MR>), grid, block, 0, a.stream, a.cavs, a.tiles,    \
-                     a.ntiles, a.xcd, a.state, a.lam_in, a.lam_out, a.dTw)
+                     a.ntiles, a.state, a.lam_in, a.lam_out, a.dTw)
   if (a.flow) { if (a.mrt) LBPC_ADJ(true, true); else LBPC_ADJ(true, false); }
   else { if (a.mrt) LBPC_ADJ(false, true); else LBPC_ADJ(false, false); }
 #undef LBPC_ADJ

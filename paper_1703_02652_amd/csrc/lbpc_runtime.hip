@@ -20,7 +20,7 @@ constexpr int kRing = 16;           // budget partial slots (steps between reduc
 constexpr int kMinTile = 64;        // smallest tile: one wavefront
 constexpr int kMaxTile = 256;       // largest tile: __launch_bounds__ of the kernels
 constexpr int kChunk = 256;         // tiles per first-pass reduction workgroup
-constexpr int kXcd = 8;             // XCDs of an MI355X: runs of the XCD-contiguous order
+constexpr int kMaxRun = 1 << 24;    // longest XCD run of tiles
 // Cells added to every population plane: keeps the planes of a cavity from
 // starting at power-of-two distances (2^21 or 2^24 cells for 128^3 / 256^3),
 // where the 26 concurrent plane streams fall on the same HBM channels.
@@ -395,7 +395,7 @@ struct lbpc_ctx {
   double* d_mpart = nullptr;  // measure pass records
   char* region[2] = {nullptr, nullptr};
   int cur = 0;
-  int block = 256, grid = 0, graph_steps = 16, xcd = kXcd;
+  int block = 256, grid = 0, graph_steps = 16, xrun = 4;
   int ntiles = 0, nchunks = 0;
   int pending = 0;
   int64_t steps = 0;
@@ -435,7 +435,6 @@ hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partia
   a.budget = budget;
   a.block = x->block;
   a.grid = x->grid;
-  a.xcd = x->xcd;
   a.flow = x->L.flow;
   a.mrt = x->L.mrt;
   a.stream = st;
@@ -488,7 +487,33 @@ void drop_graphs(lbpc_ctx* x) {
   }
 }
 
-// Tile queue for the current block size: tiles never straddle cavities.
+// Queue order for XCD runs of `run` tiles.  Queue position p = kXcds j + k
+// runs on XCD k; it gets the j-th tile of that XCD, which walks the runs k,
+// k + kXcds, k + 2 kXcds, ... of `run` consecutive tiles (in the natural order
+// of the cells).  The tiles of one run are the rows on both sides of the
+// diagonal links that cross between them: written from one XCD, the cache
+// lines that both rows write are completed in that XCD's L2 before they go to
+// memory.  Eight runs side by side keep the HBM streams sequential.  run = 1
+// is the natural order; runs longer than a kXcds-th of the queue are cut to
+// that length (one contiguous run per XCD).
+std::vector<int2> xcd_order(const std::vector<int2>& tiles, int64_t run) {
+  const int64_t m = static_cast<int64_t>(tiles.size());
+  run = std::min<int64_t>(run, (m + kXcds - 1) / kXcds);
+  if (run <= 1) return tiles;
+  std::vector<int2> q;
+  q.reserve(tiles.size());
+  const int64_t runs = (m + run - 1) / run;
+  const int64_t per_xcd = (runs + kXcds - 1) / kXcds;
+  for (int64_t j = 0; j < per_xcd * run; ++j)
+    for (int k = 0; k < kXcds; ++k) {
+      const int64_t t = (k + kXcds * (j / run)) * run + j % run;
+      if (t < m) q.push_back(tiles[t]);
+    }
+  return q;
+}
+
+// Tile queue for the current block size (tiles never straddle cavities) in
+// the XCD run order; chunks and budget partials use the natural tile index.
 int build_tiles(lbpc_ctx* x) {
   std::vector<int2> tiles;
   std::vector<int4> chunks;
@@ -505,6 +530,7 @@ int build_tiles(lbpc_ctx* x) {
   }
   x->ntiles = static_cast<int>(tiles.size());
   x->nchunks = static_cast<int>(chunks.size());
+  tiles = xcd_order(tiles, x->xrun);
   HIPCHK(x, hipMemcpyAsync(x->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
                            hipMemcpyHostToDevice, x->stream));
   HIPCHK(x, hipMemcpyAsync(x->d_chunks, chunks.data(), sizeof(int4) * chunks.size(),
@@ -862,21 +888,21 @@ int lbpc_load(lbpc_ctx* x, const void* host_buf, size_t bytes) {
 }
 
 int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t graph_steps,
-                    int32_t xcd_runs) {
+                    int32_t xcd_run) {
   if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
   if (block < kMinTile || block > kMaxTile || block % 64)
     return fail(x, LBPC_EINVAL, "block must be 64, 128, 192 or 256");
   if (grid_blocks < 0) return fail(x, LBPC_EINVAL, "grid_blocks must be >= 0");
   if (graph_steps < 0 || graph_steps > kRing || graph_steps % 2)
     return fail(x, LBPC_EINVAL, "graph_steps must be even and <= 16");
-  if (xcd_runs < 1 || xcd_runs > 64) return fail(x, LBPC_EINVAL, "xcd_runs must lie in [1, 64]");
+  if (xcd_run < 1 || xcd_run > kMaxRun) return fail(x, LBPC_EINVAL, "xcd_run must lie in [1, 2^24]");
   int rc = flush(x);
   if (rc) return rc;
   x->grid = grid_blocks;
   x->graph_steps = graph_steps;
-  x->xcd = xcd_runs;
-  if (block != x->block) {
+  if (block != x->block || xcd_run != x->xrun) {
     x->block = block;
+    x->xrun = xcd_run;
     rc = build_tiles(x);
     if (rc) return rc;
   }
@@ -885,12 +911,12 @@ int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t gra
 }
 
 int lbpc_get_launch(const lbpc_ctx* x, int32_t* block, int32_t* grid_blocks, int32_t* graph_steps,
-                    int32_t* xcd_runs) {
+                    int32_t* xcd_run) {
   if (!x) return LBPC_EINVAL;
   if (block) *block = x->block;
   if (grid_blocks) *grid_blocks = x->grid;
   if (graph_steps) *graph_steps = x->graph_steps;
-  if (xcd_runs) *xcd_runs = x->xcd;
+  if (xcd_run) *xcd_run = x->xrun;
   return LBPC_OK;
 }
 
@@ -953,7 +979,6 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   const int cus = prop.multiProcessorCount;
   const int blocks[3] = {64, 128, 256};
   const int grids[4] = {0, 2 * cus, 4 * cus, 8 * cus};
-  const int xcds[2] = {1, kXcd};
   // Trials run real, alternating steps (the cache state of a run differs from
   // re-reading one unchanged region); the state is saved to the host first and
   // restored afterwards, so tuning leaves the run untouched.
@@ -973,13 +998,13 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   // trials run the step without budget partials, so that profiles of the run
   // that follows see only the chosen launch in the partials kernels
   auto trial = [&](const Cand& k, int steps, double& per) -> int {
-    if (k.b != x->block) {
+    if (k.b != x->block || k.xc != x->xrun) {
       x->block = k.b;
+      x->xrun = k.xc;
       const int r = build_tiles(x);
       if (r) return r;
     }
     x->grid = k.g;
-    x->xcd = k.xc;
     for (int i = 0; i < 2; ++i, c ^= 1)
       HIPCHK(x, dispatch_step(x, x->region[c], x->region[c ^ 1], nullptr, 0, x->stream));
     HIPCHK(x, hipEventRecord(ev.e0, x->stream));
@@ -994,16 +1019,23 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   };
   // stage 1: every shape once; stage 2: the three fastest again, interleaved,
   // four rounds each (a drift of the box then hits all three alike)
-  Cand best{x->block, x->grid, x->xcd, 0.0};
+  Cand best{x->block, x->grid, x->xrun, 0.0};
   auto tune = [&]() -> int {
     std::vector<Cand> cands;
-    for (int b : blocks)
+    for (int b : blocks) {
+      int64_t ntiles = 0;
+      for (int64_t n : x->L.ncell) ntiles += (n + b - 1) / b;
+      // XCD runs: natural order, short runs, one contiguous run per XCD
+      const int whole = static_cast<int>((ntiles + kXcds - 1) / kXcds);
+      std::vector<int> runs = {1, 4, 16};
+      if (whole > 16) runs.push_back(whole);
       for (int g : grids)
-        for (int xc : xcds) {
+        for (int xc : runs) {
           // a persistent grid must have fewer workgroups than there are tiles
-          if (g > 0 && g >= (x->L.total_cells + b - 1) / b) continue;
+          if (g > 0 && g >= ntiles) continue;
           cands.push_back({b, g, xc, 0.0});
         }
+    }
     for (Cand& k : cands) {
       const int r = trial(k, trial_steps, k.ms);
       if (r) return r;
@@ -1034,7 +1066,7 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   x->cur = cur0;
   x->block = best.b;
   x->grid = best.g;
-  x->xcd = best.xc;
+  x->xrun = best.xc;
   rc = build_tiles(x);
   if (trc) return fail(x, trc, terr);
   if (e1 != hipSuccess || e2 != hipSuccess)
@@ -1167,7 +1199,6 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
       g.lam_out = lam[li ^ 1];
       g.dTw = dtw;
       g.block = x->block;
-      g.xcd = x->xcd;
       g.flow = flow;
       g.mrt = x->L.mrt;
       g.stream = x->stream;

@@ -153,10 +153,17 @@ def test_batch_of_uneven_cavities_matches_separate_oracle_runs():
     from paper_1703_02652_amd import Cavity
     cav = Cavity(cfgs, T0=T0s, device="cuda")
     cav.step(150)
+    b = cav.budgets()
     for i, c in enumerate(cfgs):
         f, g = cav.state(i)
-        ref = oracle.run(c, oracle.init_state(c, T0s[i]), 150)
+        ref, hist = oracle.run(c, oracle.init_state(c, T0s[i]), 150, history=True)
         assert rel(g, ref[1]) < FP64_TOL and rel(f, ref[0]) < FP64_TOL, i
+        # budgets of each cavity (the tiles of the three interleave in the queue)
+        rf = oracle.fields(c, ref)
+        assert b[i, 0] == pytest.approx(rf["h"].sum(), rel=1e-12, abs=1e-12), i
+        assert b[i, 1] == pytest.approx(rf["rho"].sum(), rel=1e-13), i
+        assert b[i, 2] == pytest.approx(rf["fl"].sum(), rel=1e-12, abs=1e-12), i
+        assert b[i, 3] == pytest.approx(hist[:, 3].sum(), rel=1e-11, abs=1e-9), i
 
 
 def test_budgets_fp64_conservation_and_wall_flux():
