@@ -191,16 +191,25 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     const View<P> st = view<P>(state, c, FLOW);
     const AdjView<R> li = adj_view<R>(lam_in, pl, FLOW);
     const AdjView<R> lo = adj_view<R>(lam_out, pl, FLOW);
+    using S = typename Fmt<P>::S;
+    using S0 = typename Fmt<P>::S0;
+    // planes through buffer resources, as in the step kernel (32-bit offsets)
+    const uint32_t pb = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(S));
+    const uint32_t pb0 = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(S0));
+    const uint32_t pbr = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(R));
+    const uint32_t oc = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
+    const uint32_t oc0 = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S0));
+    const uint32_t ocr = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(R));
     // ---- recompute the forward cell quantities
     R d[19], g[7];
     if (FLOW) {
 #pragma unroll
-      for (int a = 0; a < 19; ++a) d[a] = dec(st.f[a * pl + cell]);
+      for (int a = 0; a < 19; ++a) d[a] = dec(buf_ld<S>(plane_rsrc(st.f + a * pl, pb), oc));
     }
-    const double g0d = st.g0[cell];
+    const double g0d = buf_ld<S0>(plane_rsrc(st.g0, pb0), oc0);
     g[0] = static_cast<R>(g0d);
 #pragma unroll
-    for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
+    for (int a = 1; a < 7; ++a) g[a] = dec(buf_ld<S>(plane_rsrc(st.g + (a - 1) * pl, pb), oc));
     const R s6 = moving_sum(g);
     const double hd = g0d + static_cast<double>(s6);
     double Td, fld;
@@ -217,35 +226,62 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     const R ux = FLOW ? q.ux : R(0), uy = FLOW ? q.uy : R(0), uz = FLOW ? q.uz : R(0);
     const R sig = sigma_chi<R>(c, fl);
 
-    // ---- gather the adjoint of the post-collision populations (S^T)
+    // ---- gather the adjoint of the post-collision populations (S^T).  With
+    // walls on all six faces an interior link's source is this cell plus a
+    // shift that is uniform per cavity; a lane whose link hits a wall loads
+    // past the plane end (the hardware returns 0) and then reads its own
+    // reflected slot.  Periodic faces take link_target.
     const Site s = make_site(c, cell);
     R lf[19], lg[7];
     if (FLOW) {
-      lf[0] = li.f[cell];
+      lf[0] = buf_ld_gather<R>(plane_rsrc(li.f, pbr), ocr);
 #pragma unroll
       for (int a = 1; a < 19; ++a) {
-        int face;
-        const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
-        lf[a] = face < 0 ? li.f[a * pl + to] : li.f[Q19OPP[a] * pl + cell];
+        bool wall;
+        uint32_t from;
+        if (c.walls_only) {
+          wall = hits_wall(s, Q19X[a], Q19Y[a], Q19Z[a]);
+          const int32_t shift = Q19X[a] + Q19Y[a] * c.nx + Q19Z[a] * c.nxy;
+          from = wall ? kDrop : ocr + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(R));
+        } else {
+          int face;
+          const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
+          wall = face >= 0;
+          from = wall ? kDrop : static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(R));
+        }
+        R v = buf_ld_gather<R>(plane_rsrc(li.f + a * pl, pbr), from);
+        if (wall) v = buf_ld_gather<R>(plane_rsrc(li.f + Q19OPP[a] * pl, pbr), ocr);  // bounce-back
+        lf[a] = v;
       }
     }
-    lg[0] = li.g[cell];
+    lg[0] = buf_ld_gather<R>(plane_rsrc(li.g, pbr), ocr);
 #pragma unroll
     for (int a = 1; a < 7; ++a) {
       int face;
-      const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
-      if (face < 0) {
-        lg[a] = li.g[a * pl + to];
+      bool wall;
+      uint32_t from;
+      if (c.walls_only) {
+        face = (a & 1) ? a : a - 2;  // +x -> x+ face (1), -x -> x- face (0), ...
+        wall = hits_wall(s, Q7X[a], Q7Y[a], Q7Z[a]);
+        const int32_t shift = Q7X[a] + Q7Y[a] * c.nx + Q7Z[a] * c.nxy;
+        from = wall ? kDrop : ocr + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(R));
       } else {
-        const R back = li.g[Q7OPP[a] * pl + cell];
+        const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
+        wall = face >= 0;
+        from = wall ? kDrop : static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(R));
+      }
+      R v = buf_ld_gather<R>(plane_rsrc(li.g + a * pl, pbr), from);
+      if (wall) {
+        const R back = buf_ld_gather<R>(plane_rsrc(li.g + Q7OPP[a] * pl, pbr), ocr);
         if (c.bc[face] == BC_DIRICHLET) {
-          lg[a] = -back;
+          v = -back;
           const int64_t node = c.twface[face] + face_node(c, s, face);
           dTw[node] += c.omega_T * c.cp_ref * static_cast<double>(back);
         } else {
-          lg[a] = back;
+          v = back;
         }
       }
+      lg[a] = v;
     }
 
     // ---- transposed enthalpy collision
@@ -353,14 +389,14 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         if (Q19X[a] != 0) v += Q19X[a] > 0 ? jxb : -jxb;
         if (Q19Y[a] != 0) v += Q19Y[a] > 0 ? jyb : -jyb;
         if (Q19Z[a] != 0) v += Q19Z[a] > 0 ? jz0b : -jz0b;
-        lo.f[a * pl + cell] = v;
+        buf_st<R>(plane_rsrc(lo.f + a * pl, pbr), ocr, v);
       }
     }
     // ---- phase rule and h = sum g
     const R hb = Tb * dT_dh + flb * dfl_dh;
-    lo.g[cell] = lgo[0] + hb;
+    buf_st<R>(plane_rsrc(lo.g, pbr), ocr, lgo[0] + hb);
 #pragma unroll
-    for (int a = 1; a < 7; ++a) lo.g[a * pl + cell] = lgo[a] + hb + s6b;
+    for (int a = 1; a < 7; ++a) buf_st<R>(plane_rsrc(lo.g + a * pl, pbr), ocr, lgo[a] + hb + s6b);
   }
 }
 
