@@ -19,6 +19,16 @@
 
 namespace lbpc {
 
+// Cached loads for gathers, where neighbouring waves read the two parts of a
+// cache line.
+template <class S> __device__ __forceinline__ S buf_ld_gather(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buf_ld_gather<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
+}
+template <> __device__ __forceinline__ float buf_ld_gather<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
+}
+
 // Adjoint populations: planes of the compute type, 19 f planes (with flow)
 // then g_0..g_6, at the same plane stride as the state.
 template <class R> struct AdjView {

@@ -89,15 +89,6 @@ template <> __device__ __forceinline__ __bf16 buf_ld<__bf16>(__amdgpu_buffer_rsr
   return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(
                                         r, static_cast<int>(off), 0, kNonTemporal));
 }
-// Cached loads for gathers, where neighbouring waves read the two parts of a
-// cache line.
-template <class S> __device__ __forceinline__ S buf_ld_gather(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <> __device__ __forceinline__ double buf_ld_gather<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
-}
-template <> __device__ __forceinline__ float buf_ld_gather<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
-}
 template <> __device__ __forceinline__ void buf_st<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
   using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, static_cast<int>(off), 0, 0);
