@@ -154,6 +154,9 @@ int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
  * of xcd_run consecutive tiles (in the natural order of the cells), the runs of
  * the eight XCDs side by side.  1 is the natural order; a run longer than an
  * eighth of the queue is cut to that length (one contiguous run per XCD).
+ * Consecutive steps walk each XCD's share of the queue in opposite
+ * directions, so that an XCD first reads what it wrote last in the step before
+ * (still in its L2 and in the Infinity Cache).
  * Results do not depend on any of these settings: the state bit for bit, and
  * the budgets for a given block size. */
 int lbpc_set_launch(lbpc_ctx* ctx, int32_t block, int32_t grid_blocks, int32_t graph_steps,

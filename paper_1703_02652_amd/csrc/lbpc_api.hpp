@@ -85,6 +85,7 @@ struct StepArgs {
   const int32_t* status;        // per-cavity freeze flags
   int budget;                   // 0 none, 1 wall inflow only, 2 all partials
   int block, grid;              // grid = 0: one workgroup per tile
+  int reverse;                  // 1: walk each XCD's queue positions from their end
   int flow, mrt;
   hipStream_t stream;
 };

@@ -471,21 +471,33 @@ __device__ __forceinline__ void wave_sums(const double* v, double* sums, int til
   }
 }
 
+// Queue position that workgroup slot t takes in a reversed walk: position
+// t = kXcds j + k (XCD k) goes to the j-th last position of XCD k.
+__device__ __forceinline__ int reversed_slot(int t, int ntiles) {
+  const int k = t % kXcds, j = t / kXcds;
+  const int per_xcd = (ntiles - k + kXcds - 1) / kXcds;  // positions of XCD k
+  return (per_xcd - 1 - j) * kXcds + k;
+}
+
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
 // BUDGET: 0 no partials (recomputation inside the adjoint), 1 wall inflow only,
-// 2 all partials (h, rho, f_l, wall inflow, bad cells).
+// 2 all partials (h, rho, f_l, wall inflow, bad cells).  reverse = 1 walks the
+// queue positions of each XCD (those equal modulo kXcds) from their end:
+// consecutive steps alternate, so that each XCD first reads what it wrote last
+// in the step before, while that is still in its L2 and in the Infinity Cache,
+// and every tile stays on one XCD from step to step.
 template <int P, bool FLOW, bool MRT, int BUDGET>
 __global__ void __launch_bounds__(256)
-k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int reverse,
        const char* __restrict__ src, char* __restrict__ dst, double* __restrict__ partials,
        double* __restrict__ sums, const int32_t* __restrict__ status) {
   using S = typename Fmt<P>::S;
   using S0 = typename Fmt<P>::S0;
   using R = typename Fmt<P>::R;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int2 tl = tiles[t];
+    const int2 tl = tiles[reverse ? reversed_slot(t, ntiles) : t];
     const CavParams& c = cavs[tl.x];
     const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
     double acc[NPART] = {0.0, 0.0, 0.0, 0.0, 0.0};

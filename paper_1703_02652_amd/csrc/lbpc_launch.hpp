@@ -24,7 +24,7 @@ hipError_t launch_step(const StepArgs& a) {
   const dim3 block(a.block);
 #define LBPC_STEP(FL, MR, BU)                                                              \
   hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
-                     a.ntiles, a.src, a.dst, a.partials, a.sums, a.status)
+                     a.ntiles, a.reverse, a.src, a.dst, a.partials, a.sums, a.status)
 #define LBPC_STEP_B(FL, MR)                                    \
   do {                                                         \
     if (a.budget == 2) LBPC_STEP(FL, MR, 2);                   \

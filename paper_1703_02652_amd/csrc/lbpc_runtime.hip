@@ -395,6 +395,7 @@ struct lbpc_ctx {
   double* d_mpart = nullptr;  // measure pass records
   char* region[2] = {nullptr, nullptr};
   int cur = 0;
+  int flip = 0;                 // direction of the next step's walk of the queue
   int block = 256, grid = 0, graph_steps = 16, xrun = 4;
   int ntiles = 0, nchunks = 0;
   int pending = 0;
@@ -433,6 +434,10 @@ hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partia
   a.partials = partials;
   a.status = x->d_status;
   a.budget = budget;
+  // consecutive steps walk the tile queue in opposite directions (graphs hold
+  // an even number of steps, so replays keep the alternation)
+  a.reverse = x->flip;
+  x->flip ^= 1;
   a.block = x->block;
   a.grid = x->grid;
   a.flow = x->L.flow;
