@@ -273,13 +273,13 @@ def main():
                              "cavity128_fp64"],
                     help="cavity timed for the main line (profiling of the other kernels)")
     ap.add_argument("--launch", default=None,
-                    help="block,grid,graph_steps instead of autotuning")
+                    help="block,grid,graph_steps,xcd_run instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is not implemented", file=sys.stderr)
+        print(f"bench.py: the lbpc library runs on one GPU (asked for --gpus {args.gpus}); "
+              "a multi-GPU decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import workloads as W

@@ -1,7 +1,7 @@
 """Long-run parity of the 128^3 melting cavity (Ra 1e5, Pr 0.02, Ste 0.1):
 the FP32 GPU run against the FP64 CPU oracle over many steps.
 
-Not collected by pytest (minutes of oracle time); run on the GPU machine:
+Not collected by pytest (minutes of oracle time); run on a machine with the GPU:
     python tests/long_parity_cavity128.py --steps 10000 --every 1000
 Prints, every `every` steps, the mean liquid fraction of both, the largest
 pointwise liquid-fraction difference and the largest temperature difference.

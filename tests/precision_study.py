@@ -2,7 +2,7 @@
 FP32, shifted FP16 and shifted BF16 GPU runs against the FP64 CPU oracle.
 
 Not collected by pytest (about a minute of oracle time per Prandtl number);
-run on the GPU machine:
+run on a machine with the GPU:
     python tests/precision_study.py --n 64 --steps 2000 --every 500
 Prints, every `every` steps and for each storage format, the largest and RMS
 differences of T, f_l and |u| from the oracle and the difference of the mean
