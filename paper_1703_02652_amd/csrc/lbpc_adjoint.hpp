@@ -285,6 +285,10 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         const R back = buf_ld_gather<R>(plane_rsrc(li.g + Q7OPP[a] * pl, pbr), ocr);
         if (c.bc[face] == BC_DIRICHLET) {
           v = -back;
+          // one D3Q7 link crosses a face at each wall node, so one thread
+          // writes each accumulator per launch (no atomics needed); the
+          // adjoint runs on single-cavity contexts, whose face fields start
+          // at offset 0
           const int64_t node = c.twface[face] + face_node(c, s, face);
           dTw[node] += c.omega_T * c.cp_ref * static_cast<double>(back);
         } else {
