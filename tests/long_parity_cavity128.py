@@ -1,10 +1,19 @@
 """Long-run parity of the 128^3 melting cavity (Ra 1e5, Pr 0.02, Ste 0.1):
 the FP32 GPU run against the FP64 CPU oracle over many steps.
 
-Not collected by pytest (minutes of oracle time); run on a machine with the GPU:
+Not collected by pytest (minutes to an hour of oracle time).  Three ways to
+run it:
     python tests/long_parity_cavity128.py --steps 10000 --every 1000
+        GPU and oracle in lockstep on a machine with the GPU;
+    python tests/long_parity_cavity128.py --steps 20000 --every 1000 --record run.npz
+        the GPU run alone, saving the mean liquid fraction and the liquid
+        fraction field (float32) every `every` steps and the temperature
+        field every `t_every` steps;
+    python tests/long_parity_cavity128.py --against run.npz
+        the oracle alone (no GPU needed), compared with a recorded GPU run.
 Prints, every `every` steps, the mean liquid fraction of both, the largest
-pointwise liquid-fraction difference and the largest temperature difference.
+pointwise liquid-fraction difference and (where recorded) the largest
+temperature difference.
 """
 import argparse
 import json
@@ -21,33 +30,81 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 
+def _row(k, fl_gpu, fl_ref, T_gpu, T_ref, t0):
+    row = dict(step=k, mean_fl_gpu=float(np.mean(fl_gpu, dtype=np.float64)),
+               mean_fl_oracle=float(fl_ref.mean()),
+               max_dfl=float(np.abs(fl_gpu.astype(np.float64) - fl_ref).max()),
+               elapsed_s=round(time.time() - t0, 1))
+    if T_gpu is not None:
+        row["max_dT"] = float(np.abs(T_gpu.astype(np.float64) - T_ref).max())
+    return row
+
+
+def _summary(args_n, steps, rows):
+    return dict(summary="long parity", n=args_n, steps=steps, threads=oracle.threads(),
+                max_dfl=max(r["max_dfl"] for r in rows),
+                max_d_mean_fl=max(abs(r["mean_fl_gpu"] - r["mean_fl_oracle"]) for r in rows))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--every", type=int, default=1000)
+    ap.add_argument("--t-every", type=int, default=5000)
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--record", default=None)
+    ap.add_argument("--against", default=None)
     args = ap.parse_args()
+    t0 = time.time()
+    rows = []
+
+    if args.against:
+        rec = np.load(args.against)  # arrays written by --record (no pickles)
+        n, every = int(rec["n"]), int(rec["every"])
+        steps = rec["steps"]
+        cfg64 = W.melting_cavity(n, 1e5, 0.02, 0.1, precision=W.FP64)
+        st = oracle.init_state(cfg64)
+        done = 0
+        for i, k in enumerate(steps):
+            st = oracle.run(cfg64, st, int(k) - done)
+            done = int(k)
+            r = oracle.fields(cfg64, st)
+            key = f"T_{int(k)}"
+            T_gpu = rec[key] if key in rec.files else None
+            row = _row(int(k), rec["fl"][i], r["fl"], T_gpu, r["T"], t0)
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+        print(json.dumps(_summary(n, done, rows)), flush=True)
+        return
+
     from paper_1703_02652_amd import Cavity
     cfg64 = W.melting_cavity(args.n, 1e5, 0.02, 0.1, precision=W.FP64)
     cav = Cavity(dict(cfg64, precision=W.FP32), device="cuda")
+    if args.record:
+        steps, fls, Ts = [], [], {}
+        for k in range(args.every, args.steps + 1, args.every):
+            cav.step(args.every)
+            g = cav.fields(names=("T", "fl"))
+            steps.append(k)
+            fls.append(g["fl"].cpu().numpy().astype(np.float32))
+            if k % args.t_every == 0:
+                Ts[f"T_{k}"] = g["T"].cpu().numpy().astype(np.float32)
+            print(json.dumps(dict(step=k, mean_fl_gpu=float(g["fl"].mean()),
+                                  elapsed_s=round(time.time() - t0, 1))), flush=True)
+        np.savez_compressed(args.record, n=args.n, every=args.every, steps=np.array(steps),
+                            fl=np.stack(fls), **Ts)
+        return
+
     st = oracle.init_state(cfg64)
-    rows = []
-    t0 = time.time()
     for k in range(args.every, args.steps + 1, args.every):
         cav.step(args.every)
         st = oracle.run(cfg64, st, args.every)
         g = cav.fields(names=("T", "fl"))
         r = oracle.fields(cfg64, st)
-        row = dict(step=k, mean_fl_gpu=float(g["fl"].mean()), mean_fl_oracle=float(r["fl"].mean()),
-                   max_dfl=float(np.abs(g["fl"].cpu().numpy() - r["fl"]).max()),
-                   max_dT=float(np.abs(g["T"].cpu().numpy() - r["T"]).max()),
-                   elapsed_s=round(time.time() - t0, 1))
+        row = _row(k, g["fl"].cpu().numpy(), r["fl"], g["T"].cpu().numpy(), r["T"], t0)
         rows.append(row)
         print(json.dumps(row), flush=True)
-    print(json.dumps(dict(summary="long parity", n=args.n, steps=args.steps, threads=oracle.threads(),
-                          max_dfl=max(r["max_dfl"] for r in rows),
-                          max_d_mean_fl=max(abs(r["mean_fl_gpu"] - r["mean_fl_oracle"]) for r in rows))),
-          flush=True)
+    print(json.dumps(_summary(args.n, args.steps, rows)), flush=True)
 
 
 if __name__ == "__main__":
