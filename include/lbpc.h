@@ -165,8 +165,8 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
                     int32_t* graph_steps, int32_t* xcd_run);
 
 /* Time every candidate launch configuration (tile size 64/128/256, one
- * workgroup per tile or a persistent grid of 2, 4 or 8 workgroups per compute
- * unit, XCD runs of 1, 4, 16 tiles or one run per XCD) with trial_steps real alternating steps from the current state
+ * workgroup per tile or a persistent grid of 4 workgroups per compute unit,
+ * XCD runs of 1, 2, 4, 8, 16, 32 tiles or one run per XCD) with trial_steps real alternating steps from the current state
  * (without budget partials), re-time the three fastest four times more,
  * interleaved, and keep the fastest of those.  The state is copied to host
  * memory first and restored afterwards, so tuning does not advance the run.

@@ -983,7 +983,7 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
   HIPCHK(x, hipGetDeviceProperties(&prop, dev));
   const int cus = prop.multiProcessorCount;
   const int blocks[3] = {64, 128, 256};
-  const int grids[4] = {0, 2 * cus, 4 * cus, 8 * cus};
+  const int grids[2] = {0, 4 * cus};
   // Trials run real, alternating steps (the cache state of a run differs from
   // re-reading one unchanged region); the state is saved to the host first and
   // restored afterwards, so tuning leaves the run untouched.
@@ -1030,10 +1030,10 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
     for (int b : blocks) {
       int64_t ntiles = 0;
       for (int64_t n : x->L.ncell) ntiles += (n + b - 1) / b;
-      // XCD runs: natural order, short runs, one contiguous run per XCD
+      // XCD runs: natural order, runs of 2 to 32 tiles, one contiguous run per XCD
       const int whole = static_cast<int>((ntiles + kXcds - 1) / kXcds);
-      std::vector<int> runs = {1, 4, 16};
-      if (whole > 16) runs.push_back(whole);
+      std::vector<int> runs = {1, 2, 4, 8, 16, 32};
+      if (whole > 32) runs.push_back(whole);
       for (int g : grids)
         for (int xc : runs) {
           // a persistent grid must have fewer workgroups than there are tiles
