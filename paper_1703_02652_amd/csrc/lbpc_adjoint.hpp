@@ -188,12 +188,14 @@ __device__ __forceinline__ void flow_collide_vjp(const CavParams& c, R* lf, cons
 
 template <int P, bool FLOW, bool MRT>
 __global__ void __launch_bounds__(256)
-k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles,
+k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int reverse,
           const char* __restrict__ state, const char* __restrict__ lam_in,
           char* __restrict__ lam_out, double* __restrict__ dTw) {
   using R = typename Fmt<P>::R;
+  // consecutive adjoint steps walk the queue in opposite directions, as the
+  // forward steps do: each XCD first reads the adjoint it wrote last
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int2 tl = tiles[t];
+    const int2 tl = tiles[reverse ? reversed_slot(t, ntiles) : t];
     const CavParams& c = cavs[tl.x];
     const int32_t cell = tl.y + static_cast<int32_t>(threadIdx.x);
     if (cell >= c.n) continue;

@@ -99,6 +99,7 @@ struct AdjArgs {
   char* lam_out;                // adjoint of the state at t
   double* dTw;                  // wall-temperature gradient accumulators (per cavity block)
   int block;
+  int reverse;                  // 1: walk each XCD's queue positions from their end
   int flow, mrt;
   hipStream_t stream;
 };

@@ -92,7 +92,7 @@ hipError_t launch_adjoint(const AdjArgs& a) {
   const dim3 grid(step_grid(a.ntiles, 0)), block(a.block);
 #define LBPC_ADJ(FL, MR)                                                                    \
   hipLaunchKernelGGL((k_adjoint<P, FL, MR>), grid, block, 0, a.stream, a.cavs, a.tiles,    \
-                     a.ntiles, a.state, a.lam_in, a.lam_out, a.dTw)
+                     a.ntiles, a.reverse, a.state, a.lam_in, a.lam_out, a.dTw)
   if (a.flow) { if (a.mrt) LBPC_ADJ(true, true); else LBPC_ADJ(true, false); }
   else { if (a.mrt) LBPC_ADJ(false, true); else LBPC_ADJ(false, false); }
 #undef LBPC_ADJ

@@ -1204,6 +1204,7 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
       g.lam_out = lam[li ^ 1];
       g.dTw = dtw;
       g.block = x->block;
+      g.reverse = li;  // alternates from one adjoint step to the next
       g.flow = flow;
       g.mrt = x->L.mrt;
       g.stream = x->stream;
