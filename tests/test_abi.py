@@ -72,3 +72,15 @@ def test_config_struct_layout_matches_header():
     names = re.findall(r"\b([a-zA-Z_][a-zA-Z_0-9]*)\s*(?:\[\d+\])?\s*[,;]", body)
     assert names == [n for n, _ in LbpcConfig._fields_]
     assert ctypes.sizeof(LbpcConfig) == 6 * 4 + 6 * 4 + 6 * 8 + 17 * 8 + 7 * 8
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says why,
+    before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
