@@ -485,8 +485,9 @@ hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hip
 
 void drop_graphs(lbpc_ctx* x) {
   for (int i = 0; i < 2; ++i) {
-    if (x->gexec[i]) hipGraphExecDestroy(x->gexec[i]);
-    if (x->graph[i]) hipGraphDestroy(x->graph[i]);
+    // release paths have no caller to report a failure to
+    if (x->gexec[i]) (void)hipGraphExecDestroy(x->gexec[i]);
+    if (x->graph[i]) (void)hipGraphDestroy(x->graph[i]);
     x->gexec[i] = nullptr;
     x->graph[i] = nullptr;
   }
@@ -580,7 +581,7 @@ int capture(lbpc_ctx* x, int from) {
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(x->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return fail(x, LBPC_EHIP, std::string("graph capture: ") +
                                   hipGetErrorString(e != hipSuccess ? e : e2));
   }
@@ -616,8 +617,8 @@ struct EventPair {
     return e != hipSuccess ? e : hipEventCreate(&e1);
   }
   ~EventPair() {
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
   }
 };
 
@@ -690,7 +691,7 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
   for (int i = 0; i < batch; ++i) x->hp.push_back(make_params(cfgs[i], L, i, x->d_tw));
   auto cleanup = [&](int rc) {
     if (rc != LBPC_OK) {
-      if (x->cap) hipStreamDestroy(x->cap);
+      if (x->cap) (void)hipStreamDestroy(x->cap);
       delete x;
     }
     return rc;
@@ -727,9 +728,9 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
 
 void lbpc_destroy(lbpc_ctx* x) {
   if (!x) return;
-  if (x->stream) hipStreamSynchronize(x->stream);
+  if (x->stream) (void)hipStreamSynchronize(x->stream);
   drop_graphs(x);
-  if (x->cap) hipStreamDestroy(x->cap);
+  if (x->cap) (void)hipStreamDestroy(x->cap);
   delete x;
 }
 
