@@ -174,6 +174,25 @@ def full_run_128(launch, steps=20000):
              unstable=int(cav.status().max()))
     cav.close()
     del cav
+    # the same run again, untimed, with the budgets every tenth of it: f_l and
+    # Nu against Fo, mass drift and the enthalpy balance H(t) - H(0) = inflow
+    cav = Cavity(cfg, device="cuda")
+    cav.set_launch(*launch)
+    b0 = cav.budgets()[0]
+    chi = cfg["lambda_l"] / (cfg["rho0"] * cfg["cp_ref"])
+    hist = []
+    for k in range(1, 11):
+        cav.step(steps // 10)
+        b = cav.budgets()
+        inflow = float(b[0, 3] - b0[3])
+        hist.append(dict(step=k * (steps // 10), fo=round(chi * k * (steps // 10) / 128**2, 5),
+                         mean_fl=round(float(b[0, 2]) / 128**3, 6),
+                         nusselt=round(float(cav.nusselt(b=b)), 4),
+                         mass_drift=float(b[0, 1] / b0[1] - 1.0),
+                         enthalpy_balance=float((b[0, 0] - b0[0] - inflow) / max(abs(inflow), 1.0))))
+    r["history"] = hist
+    cav.close()
+    del cav
     torch.cuda.empty_cache()
     return r
 
