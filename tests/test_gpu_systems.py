@@ -76,6 +76,28 @@ def _state_bytes_i(cav, i):
     return [g.cpu().numpy(), f.cpu().numpy()]
 
 
+def test_graph_replays_match_eager_steps_every_replay():
+    """The captured 16-step graph (with its in-graph reduction) replayed five
+    times, with an eager budget pass and a host synchronisation between the
+    replays, against the same steps launched one by one: state and budgets
+    agree bit for bit after every replay."""
+    cfg = W.melting_cavity(24, 1e5, 0.02, 0.1, precision=W.FP32)
+    cfg.update(ny=19, nz=13)
+    walls = {0: W.hot_wall_field(19, 13)}
+    g = make_cavity(cfg, walls=walls)
+    e = make_cavity(cfg, walls=walls)
+    g.set_launch(128, 0, 16, 4)
+    e.set_launch(128, 0, 0, 4)
+    for replay in range(5):
+        g.step(16)
+        e.step(16)
+        bg, be = g.budgets(), e.budgets()
+        for x, y in zip(_state_bytes(g), _state_bytes(e)):
+            assert np.array_equal(x, y), replay
+        assert np.array_equal(bg, be), replay
+        assert bg[0, 4] == 16 * (replay + 1)
+
+
 def test_autotune_does_not_advance_state():
     cfg = W.melting_cavity(16, 1e5, 0.02, 0.1, precision=W.FP32)
     a = make_cavity(cfg)
