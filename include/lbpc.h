@@ -149,11 +149,13 @@ int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
  * multiple of 64; grid_blocks: 0 for one workgroup per tile, else a persistent
  * grid (rounded up to a multiple of 8) that strides over the tile queue;
  * graph_steps: steps per captured HIP graph (even, at most 16, 0 disables
- * graphs); xcd_run: 1..2^24, the queue order.  The MI355X dispatcher sends
- * workgroup b to XCD b mod 8; the queue is ordered so that each XCD walks runs
- * of xcd_run consecutive tiles (in the natural order of the cells), the runs of
- * the eight XCDs side by side.  1 is the natural order; a run longer than an
- * eighth of the queue is cut to that length (one contiguous run per XCD).
+ * graphs); xcd_run: 0..2^24, the queue order.  The MI355X dispatcher sends
+ * workgroup b to XCD b mod 8; for xcd_run >= 1 the queue is ordered so that
+ * each XCD walks runs of xcd_run consecutive tiles (in the natural order of
+ * the cells), the runs of the eight XCDs side by side.  1 is the natural
+ * order; a run longer than an eighth of the queue is cut to that length (one
+ * contiguous run per XCD).  xcd_run = 0: XCD k takes the tiles whose first row
+ * lies in the k-th eighth of the y range, slab after slab.
  * Consecutive steps walk each XCD's share of the queue in opposite
  * directions, so that an XCD first reads what it wrote last in the step before
  * (still in its L2 and in the Infinity Cache).
@@ -166,7 +168,8 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
 
 /* Time every candidate launch configuration (tile size 64/128/256, one
  * workgroup per tile or a persistent grid of 4 workgroups per compute unit,
- * XCD runs of 1, 2, 4, 8, 16, 32 tiles or one run per XCD) with trial_steps real alternating steps from the current state
+ * y-blocks per XCD, XCD runs of 1, 2, 4, 8, 16, 32 tiles or one run per XCD)
+ * with trial_steps real alternating steps from the current state
  * (without budget partials), re-time the three fastest four times more,
  * interleaved, and keep the fastest of those.  The state is copied to host
  * memory first and restored afterwards, so tuning does not advance the run.

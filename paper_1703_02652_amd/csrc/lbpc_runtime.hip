@@ -518,8 +518,29 @@ std::vector<int2> xcd_order(const std::vector<int2>& tiles, int64_t run) {
   return q;
 }
 
+// Queue order with one y-block per XCD: XCD k takes the tiles whose first row
+// lies in the k-th eighth of the y range, slab after slab, so that the rows on
+// both sides of every y- or z-crossing link are written from one XCD, a few
+// dozen tiles apart.  Queue position kXcds j + k again holds XCD k's j-th tile.
+std::vector<int2> yblock_order(const std::vector<int2>& tiles, const std::vector<lbpc_config>& cfg) {
+  std::vector<std::vector<int2>> seq(kXcds);
+  for (const int2& t : tiles) {
+    const lbpc_config& c = cfg[static_cast<size_t>(t.x)];
+    const int64_t y = (t.y / c.nx) % c.ny;
+    seq[static_cast<size_t>(y * kXcds / c.ny)].push_back(t);
+  }
+  size_t longest = 0;
+  for (const auto& v : seq) longest = std::max(longest, v.size());
+  std::vector<int2> q;
+  q.reserve(tiles.size());
+  for (size_t j = 0; j < longest; ++j)
+    for (int k = 0; k < kXcds; ++k)
+      if (j < seq[static_cast<size_t>(k)].size()) q.push_back(seq[static_cast<size_t>(k)][j]);
+  return q;
+}
+
 // Tile queue for the current block size (tiles never straddle cavities) in
-// the XCD run order; chunks and budget partials use the natural tile index.
+// the XCD order; chunks and budget partials use the natural tile index.
 int build_tiles(lbpc_ctx* x) {
   std::vector<int2> tiles;
   std::vector<int4> chunks;
@@ -536,7 +557,7 @@ int build_tiles(lbpc_ctx* x) {
   }
   x->ntiles = static_cast<int>(tiles.size());
   x->nchunks = static_cast<int>(chunks.size());
-  tiles = xcd_order(tiles, x->xrun);
+  tiles = x->xrun == 0 ? yblock_order(tiles, x->cfg) : xcd_order(tiles, x->xrun);
   HIPCHK(x, hipMemcpyAsync(x->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
                            hipMemcpyHostToDevice, x->stream));
   HIPCHK(x, hipMemcpyAsync(x->d_chunks, chunks.data(), sizeof(int4) * chunks.size(),
@@ -901,7 +922,7 @@ int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t gra
   if (grid_blocks < 0) return fail(x, LBPC_EINVAL, "grid_blocks must be >= 0");
   if (graph_steps < 0 || graph_steps > kRing || graph_steps % 2)
     return fail(x, LBPC_EINVAL, "graph_steps must be even and <= 16");
-  if (xcd_run < 1 || xcd_run > kMaxRun) return fail(x, LBPC_EINVAL, "xcd_run must lie in [1, 2^24]");
+  if (xcd_run < 0 || xcd_run > kMaxRun) return fail(x, LBPC_EINVAL, "xcd_run must lie in [0, 2^24]");
   int rc = flush(x);
   if (rc) return rc;
   x->grid = grid_blocks;
@@ -1031,9 +1052,10 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
     for (int b : blocks) {
       int64_t ntiles = 0;
       for (int64_t n : x->L.ncell) ntiles += (n + b - 1) / b;
-      // XCD runs: natural order, runs of 2 to 32 tiles, one contiguous run per XCD
+      // queue orders: one y-block per XCD (0), natural order (1), XCD runs of
+      // 2 to 32 tiles, one contiguous run per XCD
       const int whole = static_cast<int>((ntiles + kXcds - 1) / kXcds);
-      std::vector<int> runs = {1, 2, 4, 8, 16, 32};
+      std::vector<int> runs = {0, 1, 2, 4, 8, 16, 32};
       if (whole > 32) runs.push_back(whole);
       for (int g : grids)
         for (int xc : runs) {

@@ -28,7 +28,7 @@ def test_launch_shapes_and_graphs_are_bitwise_identical():
     walls = {0: W.hot_wall_field(13, 11)}
     ref = None
     for launch in [(256, 0, 16, 8), (64, 0, 0, 1), (128, 37, 4, 8), (256, 512, 0, 1),
-                   (192, 0, 2, 3), (64, 24, 16, 8)]:
+                   (192, 0, 2, 3), (64, 24, 16, 8), (256, 0, 16, 0), (64, 40, 4, 0)]:
         cav = make_cavity(cfg, walls=walls)
         cav.set_launch(*launch)
         cav.step(53)
@@ -43,7 +43,8 @@ def test_launch_shapes_and_graphs_are_bitwise_identical():
 
 def test_queue_order_and_grid_do_not_change_state_or_budgets():
     """A batch of three cavities whose tiles interleave in the queue: XCD runs
-    of 1, 3, 16 tiles and one run per XCD, with and without a persistent grid,
+    of 1, 3, 16 tiles, one run per XCD and y-blocks per XCD, with and without a
+    persistent grid,
     give the same state and the same budgets bit for bit (the budget partials
     are indexed by the natural tile order)."""
     from paper_1703_02652_amd import Cavity
@@ -55,7 +56,7 @@ def test_queue_order_and_grid_do_not_change_state_or_budgets():
     T0s = [W.random_temperature(c, seed=40 + i, lo=-0.2, hi=1.0) for i, c in enumerate(cfgs)]
     ref = None
     for launch in [(128, 0, 16, 1), (128, 0, 16, 3), (128, 40, 8, 16), (128, 0, 4, 1 << 20),
-                   (128, 16, 0, 4)]:
+                   (128, 16, 0, 4), (128, 0, 16, 0), (128, 24, 2, 0)]:
         cav = Cavity(cfgs, T0=T0s, device="cuda")
         cav.set_launch(*launch)
         assert cav.get_launch() == launch
@@ -157,7 +158,7 @@ def test_invalid_arguments_raise():
     with pytest.raises(LbpcError):
         cav.set_launch(256, 0, 3)
     with pytest.raises(LbpcError):
-        cav.set_launch(256, 0, 16, 0)
+        cav.set_launch(256, 0, 16, -1)
     with pytest.raises(LbpcError):
         cav.set_wall_T(2, np.zeros((8, 8)))   # adiabatic face
     import ctypes
