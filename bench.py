@@ -107,7 +107,7 @@ def precision_errors(n=256, steps=5000):
     return dict(cells=n**3, steps=steps, errors=out)
 
 
-def cpu_baseline(cfg, target_s=12.0, max_steps=400):
+def cpu_baseline(cfg, target_s=15.0, max_steps=400):
     """The FP64 CPU oracle on the same workload, a bounded number of steps
     (about target_s seconds, sized from a short probe after one warm-up step)."""
     import oracle
