@@ -24,7 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL = {0: 416, 1: 216, 2: 116, 3: 116}   # 25 planes + FP64 g_0, read + written once
+BYTES_PER_CELL = {0: 416, 1: 216, 2: 108, 3: 108}   # 25 planes + g_0 (FP64; FP32 for 16-bit), read + written once
 
 
 def measured_traffic():

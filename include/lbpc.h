@@ -53,9 +53,9 @@ enum {
 };
 
 /* Population storage.  The shifted formats store f_a - w_a rho0 (the deviation
- * from rest); g_0, which carries the latent heat, is FP64 in every format and
- * the enthalpy -> (T, f_l) update is FP64; collision arithmetic is FP32 for
- * every format but FP64. */
+ * from rest); g_0, which carries the latent heat, is FP64 in the FP64 and FP32
+ * formats and FP32 in the 16-bit ones; the enthalpy -> (T, f_l) update is
+ * FP64 and collision arithmetic FP32 for every format but FP64. */
 enum { LBPC_FP64 = 0, LBPC_FP32 = 1, LBPC_FP16S = 2, LBPC_BF16S = 3 };
 enum { LBPC_SRT = 0, LBPC_MRT = 1 };
 

@@ -152,7 +152,7 @@ struct Layout {
 };
 
 size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
-size_t g0_bytes(int) { return 8; }  // g_0 is FP64 in every storage format
+size_t g0_bytes(int prec) { return prec <= 1 ? 8 : 4; }  // g_0: FP64, or FP32 in the 16-bit formats
 
 int64_t face_size(const lbpc_config& c, int face) {
   const int d = face / 2;
