@@ -208,6 +208,14 @@ int lbpc_adjoint_forward(lbpc_ctx* ctx, int64_t nsteps, int32_t ckpt_every, int3
                          void* dev_adj_ws, size_t bytes, double* host_loss);
 int lbpc_adjoint_backward(lbpc_ctx* ctx, double seed, double* dev_dL_dTw, double* dev_dL_dT0);
 
+/* Both passes in one call: lbpc_adjoint_forward(ctx, nsteps, ckpt_every, loss,
+ * dev_adj_ws, bytes, host_loss), then lbpc_adjoint_backward with seed 1, so
+ * that dev_dL_dTw and dev_dL_dT0 (each nullable) receive dL/dT_w and dL/dT0 of
+ * the loss.  The state is left at the final step.  Synchronises. */
+int lbpc_adjoint(lbpc_ctx* ctx, int64_t nsteps, int32_t ckpt_every, int32_t loss,
+                 void* dev_adj_ws, size_t bytes, double* dev_dL_dTw, double* dev_dL_dT0,
+                 double* host_loss);
+
 void lbpc_destroy(lbpc_ctx* ctx);
 const char* lbpc_last_error(const lbpc_ctx* ctx);
 const char* lbpc_version(void);

@@ -21,7 +21,7 @@ EXPORTS = (
     "lbpc_budgets", "lbpc_status", "lbpc_get_state", "lbpc_set_state", "lbpc_state_bytes",
     "lbpc_save", "lbpc_load", "lbpc_set_launch", "lbpc_get_launch", "lbpc_autotune",
     "lbpc_time_step_kernel", "lbpc_adjoint_workspace_bytes", "lbpc_adjoint_forward",
-    "lbpc_adjoint_backward", "lbpc_destroy", "lbpc_last_error", "lbpc_version",
+    "lbpc_adjoint_backward", "lbpc_adjoint", "lbpc_destroy", "lbpc_last_error", "lbpc_version",
 )
 
 
@@ -100,6 +100,7 @@ def lib():
     L.lbpc_adjoint_workspace_bytes.restype = sz
     L.lbpc_adjoint_forward.argtypes = [vp, i64, i32, i32, vp, sz, dp]
     L.lbpc_adjoint_backward.argtypes = [vp, ctypes.c_double, vp, vp]
+    L.lbpc_adjoint.argtypes = [vp, i64, i32, i32, vp, sz, vp, vp, dp]
     L.lbpc_destroy.argtypes = [vp]
     L.lbpc_destroy.restype = None
     L.lbpc_last_error.argtypes = [vp]
@@ -108,7 +109,7 @@ def lib():
     for name in ("lbpc_create", "lbpc_set_wall_T", "lbpc_step", "lbpc_fields", "lbpc_budgets",
                  "lbpc_status", "lbpc_get_state", "lbpc_set_state", "lbpc_save", "lbpc_load",
                  "lbpc_set_launch", "lbpc_get_launch", "lbpc_autotune", "lbpc_time_step_kernel",
-                 "lbpc_adjoint_forward", "lbpc_adjoint_backward"):
+                 "lbpc_adjoint_forward", "lbpc_adjoint_backward", "lbpc_adjoint"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

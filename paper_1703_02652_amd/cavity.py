@@ -228,6 +228,28 @@ class Cavity:
             ctypes.c_void_p(dt0.data_ptr() if dt0 is not None else 0)))
         return dtw, dt0
 
+    def adjoint(self, nsteps, ckpt_every=100, loss=0, want_T0=False):
+        """Forward and reverse sweep in one library call (lbpc_adjoint).
+        Returns (loss, dL/dT_w of every face concatenated, dL/dT0 or None)."""
+        torch = _torch()
+        need = self._L.lbpc_adjoint_workspace_bytes(self._ctx, int(nsteps), int(ckpt_every))
+        if need == 0:
+            raise LbpcError(-1, "bad adjoint arguments")
+        if self._adj_ws is None or self._adj_ws.numel() < need + 256:
+            self._adj_ws = None
+            self._adj_ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._adj_ws.data_ptr() + 255) // 256 * 256
+        c = self.cfgs[0]
+        nw = 2 * (c["ny"] * c["nz"] + c["nx"] * c["nz"] + c["nx"] * c["ny"])
+        dtw = torch.empty(nw, dtype=torch.float64, device=self.device)
+        dt0 = torch.empty(self.shape(0), dtype=torch.float64, device=self.device) if want_T0 else None
+        val = ctypes.c_double()
+        self._check(self._L.lbpc_adjoint(
+            self._ctx, int(nsteps), int(ckpt_every), int(loss), ctypes.c_void_p(ptr), need,
+            ctypes.c_void_p(dtw.data_ptr()), ctypes.c_void_p(dt0.data_ptr() if dt0 is not None else 0),
+            ctypes.byref(val)))
+        return val.value, dtw, dt0
+
     def face_slice(self, flat, face, cavity=0):
         """View of one face inside a concatenated node-field vector."""
         c = self.cfgs[cavity]

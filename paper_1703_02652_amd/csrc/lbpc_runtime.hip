@@ -1245,4 +1245,11 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
   return LBPC_OK;
 }
 
+int lbpc_adjoint(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t loss, void* dev_adj_ws,
+                 size_t bytes, double* dev_dL_dTw, double* dev_dL_dT0, double* host_loss) {
+  const int rc = lbpc_adjoint_forward(x, nsteps, every, loss, dev_adj_ws, bytes, host_loss);
+  if (rc) return rc;
+  return lbpc_adjoint_backward(x, 1.0, dev_dL_dTw, dev_dL_dT0);
+}
+
 }  // extern "C"

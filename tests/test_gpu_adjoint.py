@@ -131,7 +131,7 @@ def test_autograd_function_matches_adjoint():
     cav.set_wall_T(0, Tw.detach())
     L2 = cav.adjoint_forward(40, 10)
     dtw, _ = cav.adjoint_backward(seed=2.5)
-    assert float(loss) == pytest.approx(L2, rel=1e-14)
+    assert float(loss.detach()) == pytest.approx(L2, rel=1e-14)
     assert np.allclose(2.5 * g1, cav.face_slice(dtw, 0).cpu().numpy(), rtol=1e-14, atol=0)
 
 
@@ -188,3 +188,22 @@ def test_adjoint_with_a_snapshot_of_every_step_equals_segments():
     assert np.array_equal(g1, g7)
     assert np.array_equal(d1, d7) and np.array_equal(t1, t7)
     assert np.abs(d1).max() > 1e-3
+
+
+def test_single_call_adjoint_equals_forward_then_backward():
+    """lbpc_adjoint (both passes in one call) gives the loss, the final state
+    and the gradients of lbpc_adjoint_forward followed by lbpc_adjoint_backward
+    with seed 1, bit for bit (FP64, checkpoints every 6 of 40 steps)."""
+    cfg = W.melting_cavity(9, 1e5, 0.5, 0.2, precision=W.FP64)
+    cfg.update(ny=7, nz=6)
+    walls = {0: W.hot_wall_field(7, 6)}
+    a = make_cavity(cfg, walls=walls)
+    La = a.adjoint_forward(40, 6)
+    da, ta = a.adjoint_backward(want_T0=True)
+    b = make_cavity(cfg, walls=walls)
+    Lb, db, tb = b.adjoint(40, 6, want_T0=True)
+    assert La == Lb
+    assert np.array_equal(da.cpu().numpy(), db.cpu().numpy())
+    assert np.array_equal(ta.cpu().numpy(), tb.cpu().numpy())
+    assert np.array_equal(a.state()[1].cpu().numpy(), b.state()[1].cpu().numpy())
+    assert np.abs(db.cpu().numpy()).max() > 1e-4
