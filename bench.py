@@ -24,7 +24,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL = {0: 416, 1: 216, 2: 108, 3: 108}   # 25 planes + g_0 (FP64; FP32 for 16-bit), read + written once
+# Algorithmic bytes per cell update: the 26 populations read once and written
+# once in the storage type (FP64 416, FP32 208, 16-bit populations with an FP32
+# g_0 108).  The roofline fraction uses these.
+BYTES_PER_CELL = {0: 416, 1: 208, 2: 108, 3: 108}
+# Bytes the storage format actually moves: the FP32 format keeps g_0 in FP64
+# (25 x 4 + 8 = 108 B per copy), the others match the algorithmic count.
+FORMAT_BYTES_PER_CELL = {0: 416, 1: 216, 2: 108, 3: 108}
 
 
 def measured_traffic():
@@ -197,7 +203,7 @@ def full_run_128(launch, steps=20000):
     return r
 
 
-def adjoint_ratio(prec, n=96, steps=200, every=100):
+def adjoint_ratio(prec, n=96, steps=2000, every=100):
     import torch
     import workloads as W
     from paper_1703_02652_amd import Cavity
@@ -323,11 +329,17 @@ def main():
     cav, main_r = run_cavity(cfg, args.steps, args.warmup, launch=launch, label=args.workload)
     alg_bytes = BYTES_PER_CELL[prec] * cells
     achieved = alg_bytes / (main_r["kernel_ms"] * 1e-3) / 1e9
+    step_gbs = alg_bytes / (main_r["ms_per_step"] * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic() if args.workload == "cavity128_fp32" else None,
                     kernel=f"k_step<{args.workload.split('_')[1]}, flow, MRT, wall-inflow partials>",
-                    bytes_per_launch=alg_bytes, kernel_ms=round(main_r["kernel_ms"], 5))
+                    bytes_per_cell=BYTES_PER_CELL[prec], bytes_per_launch=alg_bytes,
+                    format_bytes_per_cell=FORMAT_BYTES_PER_CELL[prec],
+                    kernel_ms=round(main_r["kernel_ms"], 5),
+                    time_source="mean duration of the step kernel, HIP events on the library's "
+                                "stream around runs of back-to-back launches",
+                    frac_of_step=round(step_gbs / HBM_PEAK_GBS, 4))
     cav.close()
     del cav
 

@@ -105,25 +105,46 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
                 const double* dev_T0, void* hip_stream, lbpc_ctx** out);
 
 /* Replace the temperature of one fixed-temperature face by a per-node field
- * (FP64 device array, copied).  Node layout: x faces [nz][ny], y faces
- * [nz][nx], z faces [ny][nx]. */
+ * (FP64 device array, copied; the caller keeps ownership).  The wall enters
+ * through the anti-bounce-back rule g_abar(x) = -g*_a(x) + 2 w_a C_p,ref T_w
+ * of every link that crosses the face: the isothermal walls of the paper's
+ * cavity problems (Sec. 3.2.2, 3.3: hot wall at T_h, cold wall at T_m), here
+ * with a temperature per wall node.  Node layout: x faces [nz][ny], y faces
+ * [nz][nx], z faces [ny][nx].  Synchronises the stream (the face mean is kept
+ * on the host for the Nusselt number of lbpc_budgets).  LBPC_EINVAL for a bad
+ * cavity or face, a face that is not LBPC_DIRICHLET, or a null field. */
 int lbpc_set_wall_T(lbpc_ctx* ctx, int32_t cavity, int32_t face, const double* dev_Tw);
 
-/* Advance every cavity by nsteps time steps (asynchronous).  Returns
- * LBPC_EUNSTABLE, without stepping, once a cavity has been flagged. */
+/* Advance every cavity by nsteps time steps (asynchronous).  One step is
+ * Eq. (5) for g and Eq. (50) for f: both collisions (Eq. (6)-(8) or (21)-(25),
+ * and (49)-(54)) take the macroscopic fields of the same pre-collision state
+ * (h, T, f_l by Eq. (2); rho, u by Eq. (55)-(56)), then both distributions
+ * stream with the wall rules above.  Steps run in captured HIP graphs of up
+ * to graph_steps steps (lbpc_set_launch), each closed by the FP64 budget
+ * reduction; an odd last step runs eagerly.  Returns LBPC_EINVAL for
+ * nsteps < 0 and LBPC_EUNSTABLE, without stepping, once a cavity has been
+ * flagged. */
 int lbpc_step(lbpc_ctx* ctx, int64_t nsteps);
 
 /* Macroscopic fields of the current (pre-collision) state of one cavity, FP64
- * planes of nx*ny*nz values in mask-bit order; u is the forced velocity
- * u = f_l (sum f e + F_b / 2) / rho (zero without flow). */
+ * planes of nx*ny*nz values in mask-bit order into caller-owned dev_out:
+ * h = sum_a g_a (Eq. (2)), T and f_l by the enthalpy rule of Eq. (2),
+ * rho = sum f (Eq. (56)) and the forced velocity u = f_l (sum f e + F_b / 2)
+ * / rho with F_b of Eq. (55) (zero without flow).  Asynchronous.
+ * LBPC_EINVAL for a bad cavity, mask 0 or above 31, or a null output. */
 int lbpc_fields(lbpc_ctx* ctx, int32_t cavity, uint32_t mask, double* dev_out);
 
-/* Per cavity, 6 FP64 values: H = sum h, mass = sum rho, sum f_l (current
- * state), the enthalpy that entered through fixed-temperature walls since
- * creation, the number of steps taken, and the enthalpy the next step lets in
- * through the x- face if it has a fixed temperature (exact lattice flux of the
- * anti-bounce-back links; the wall heat flux behind the Nusselt number of
- * Eq. (65)).  Deterministic summation order.  Synchronises the stream. */
+/* Per cavity, 7 FP64 values into host_out[7 * cavity + k]: H = sum h,
+ * mass = sum rho, sum f_l (current state), the enthalpy that entered through
+ * fixed-temperature walls since creation, the number of steps taken, the
+ * enthalpy q that the next step lets in through the x- face if it has a
+ * fixed temperature (exact lattice flux of the anti-bounce-back links), and
+ * the mean Nusselt number of that face, Eq. (65) (Sec. 3.2.2, 3.3):
+ * Nu = q nx / (ny nz chi_l C_p,ref dT), the lattice heat flux per wall node
+ * over the conductive flux chi_l C_p,ref dT / nx across the cavity, with
+ * chi_l = lambda_l / (rho0 C_p,ref) and dT = (mean wall temperature of the
+ * face) - T_m; NaN when the x- face is not fixed-temperature or dT = 0.
+ * Deterministic summation order.  Synchronises the stream. */
 int lbpc_budgets(lbpc_ctx* ctx, double* host_out);
 
 /* Per-cavity status bits (1 = non-finite or out-of-bound state seen; such a
@@ -145,8 +166,8 @@ size_t lbpc_state_bytes(const lbpc_ctx* ctx);
 int lbpc_save(lbpc_ctx* ctx, void* host_buf, size_t bytes);
 int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
 
-/* Launch configuration.  block: threads (and cells) per tile, 64..256, a
- * multiple of 64; grid_blocks: 0 for one workgroup per tile, else a persistent
+/* Launch configuration.  block: threads (and cells) per tile, 64, 128, 192
+ * or 256; grid_blocks: 0 for one workgroup per tile, else a persistent
  * grid (rounded up to a multiple of 8) that strides over the tile queue;
  * graph_steps: steps per captured HIP graph (even, at most 16, 0 disables
  * graphs); xcd_run: 0..2^24, the queue order.  The MI355X dispatcher sends

@@ -26,6 +26,7 @@ constexpr int kMaxRun = 1 << 24;    // longest XCD run of tiles
 // where the 26 concurrent plane streams fall on the same HBM channels.
 constexpr int64_t kPlanePad = 256;
 constexpr size_t kAlign = 256;
+constexpr int kBudgetValues = 7;    // values per cavity returned by lbpc_budgets
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
@@ -241,7 +242,11 @@ Layout make_layout(const lbpc_config* cfgs, int batch) {
     const int64_t ct = (n + kMinTile - 1) / kMinTile;
     tiles += ct;
     chunks += (ct + kChunk - 1) / kChunk;
-    waves += (n + kMaxTile - 1) / kMaxTile * (kMaxTile / 64);  // any tile size
+    // wavefronts of the tile queue for the tile size that needs the most of
+    // them (the empty tail waves of the last tile write zero partials too)
+    int64_t w = 0;
+    for (int64_t b = kMinTile; b <= kMaxTile; b += kMinTile) w = std::max(w, (n + b - 1) / b * (b / 64));
+    waves += w;
     std::array<int64_t, 6> tf;
     int64_t fo = 0;
     for (int f = 0; f < 6; ++f) {
@@ -380,6 +385,7 @@ struct lbpc_ctx {
   Layout L;
   std::vector<lbpc_config> cfg;
   std::vector<CavParams> hp;
+  std::vector<std::array<double, 6>> tw_mean;  // mean wall temperature of every face
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
   char* ws = nullptr;
@@ -401,8 +407,9 @@ struct lbpc_ctx {
   int pending = 0;
   int64_t steps = 0;
   bool unstable = false;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  hipGraph_t graph[2] = {nullptr, nullptr};
+  // captured graphs of 2, 4, ..., kRing steps from either state region
+  hipGraphExec_t gexec[2][kRing / 2 + 1] = {};
+  hipGraph_t graph[2][kRing / 2 + 1] = {};
   std::string err;
   AdjointPlan adj;
 };
@@ -484,13 +491,14 @@ hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hip
 }
 
 void drop_graphs(lbpc_ctx* x) {
-  for (int i = 0; i < 2; ++i) {
-    // release paths have no caller to report a failure to
-    if (x->gexec[i]) (void)hipGraphExecDestroy(x->gexec[i]);
-    if (x->graph[i]) (void)hipGraphDestroy(x->graph[i]);
-    x->gexec[i] = nullptr;
-    x->graph[i] = nullptr;
-  }
+  for (int i = 0; i < 2; ++i)
+    for (int k = 0; k <= kRing / 2; ++k) {
+      // release paths have no caller to report a failure to
+      if (x->gexec[i][k]) (void)hipGraphExecDestroy(x->gexec[i][k]);
+      if (x->graph[i][k]) (void)hipGraphDestroy(x->graph[i][k]);
+      x->gexec[i][k] = nullptr;
+      x->graph[i][k] = nullptr;
+    }
 }
 
 // Queue order for XCD runs of `run` tiles.  Queue position p = kXcds j + k
@@ -557,6 +565,10 @@ int build_tiles(lbpc_ctx* x) {
   }
   x->ntiles = static_cast<int>(tiles.size());
   x->nchunks = static_cast<int>(chunks.size());
+  // every wavefront of the queue owns one slot of each partial array
+  if (static_cast<int64_t>(x->ntiles) * (x->block / 64) > x->L.max_waves ||
+      x->nchunks > x->L.max_chunks || x->ntiles > x->L.max_tiles)
+    return fail(x, LBPC_EINVAL, "tile queue larger than the workspace layout");
   tiles = x->xrun == 0 ? yblock_order(tiles, x->cfg) : xcd_order(tiles, x->xrun);
   HIPCHK(x, hipMemcpyAsync(x->d_tiles, tiles.data(), sizeof(int2) * tiles.size(),
                            hipMemcpyHostToDevice, x->stream));
@@ -587,18 +599,17 @@ int eager_step(lbpc_ctx* x) {
   return LBPC_OK;
 }
 
-// Capture graph_steps steps plus their reduction, starting from region `from`.
-int capture(lbpc_ctx* x, int from) {
+// Capture `count` (even) steps plus their reduction, starting from region `from`.
+int capture(lbpc_ctx* x, int from, int count) {
   HIPCHK(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
   int c = from;
   hipError_t e = hipSuccess;
-  for (int i = 0; i < x->graph_steps && e == hipSuccess; ++i) {
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
     double* part = x->d_part + static_cast<int64_t>(i) * x->L.max_waves;
-    e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, i + 1 == x->graph_steps ? 2 : 1,
-                      x->cap);
+    e = dispatch_step(x, x->region[c], x->region[c ^ 1], part, i + 1 == count ? 2 : 1, x->cap);
     c ^= 1;
   }
-  if (e == hipSuccess) e = reduce(x, x->d_part, x->graph_steps, 0, x->cap);
+  if (e == hipSuccess) e = reduce(x, x->d_part, count, 0, x->cap);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(x->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -606,21 +617,40 @@ int capture(lbpc_ctx* x, int from) {
     return fail(x, LBPC_EHIP, std::string("graph capture: ") +
                                   hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  x->graph[from] = g;
-  HIPCHK(x, hipGraphInstantiate(&x->gexec[from], g, nullptr, nullptr, 0));
+  x->graph[from][count / 2] = g;
+  HIPCHK(x, hipGraphInstantiate(&x->gexec[from][count / 2], g, nullptr, nullptr, 0));
   return LBPC_OK;
 }
 
-int run_steps(lbpc_ctx* x, int64_t n) {
-  while (n > 0) {
-    if (x->graph_steps > 0 && x->pending == 0 && n >= x->graph_steps) {
-      if (!x->gexec[x->cur]) {
-        const int rc = capture(x, x->cur);
+// Every graph a run can use (2, 4, ..., graph_steps steps from either
+// region), captured together the first time one is needed, so that capture
+// and instantiation cost no time later in the run.
+int ensure_graphs(lbpc_ctx* x) {
+  for (int from = 0; from < 2; ++from)
+    for (int count = 2; count <= x->graph_steps; count += 2)
+      if (!x->gexec[from][count / 2]) {
+        const int rc = capture(x, from, count);
         if (rc) return rc;
       }
-      HIPCHK(x, hipGraphLaunch(x->gexec[x->cur], x->stream));
-      x->steps += x->graph_steps;
-      n -= x->graph_steps;
+  return LBPC_OK;
+}
+
+// Steps go into graphs of graph_steps steps, and a shorter even remainder
+// into a graph of its own; partials left by eager steps are reduced first, so
+// every graph starts on an empty ring.  Only an odd last step runs eagerly.
+int run_steps(lbpc_ctx* x, int64_t n) {
+  while (n > 0) {
+    if (x->graph_steps > 0 && n >= 2) {
+      int rc = flush(x);
+      if (rc) return rc;
+      const int count = static_cast<int>(std::min<int64_t>(x->graph_steps, n / 2 * 2));
+      if (!x->gexec[x->cur][count / 2]) {
+        rc = ensure_graphs(x);
+        if (rc) return rc;
+      }
+      HIPCHK(x, hipGraphLaunch(x->gexec[x->cur][count / 2], x->stream));
+      x->steps += count;
+      n -= count;
     } else {
       const int rc = eager_step(x);
       if (rc) return rc;
@@ -647,6 +677,31 @@ int check_cavity(lbpc_ctx* x, int cavity) {
   if (!x) return fail(nullptr, LBPC_EINVAL, "null context");
   if (cavity < 0 || cavity >= x->L.batch) return fail(x, LBPC_EINVAL, "cavity index out of range");
   return LBPC_OK;
+}
+
+// Mean of a wall-temperature field (exactly the value of a uniform field).
+double face_mean(const double* v, int64_t m) {
+  double sum = 0.0;
+  bool uniform = true;
+  for (int64_t k = 0; k < m; ++k) {
+    sum += v[k];
+    uniform = uniform && v[k] == v[0];
+  }
+  return uniform ? v[0] : sum / static_cast<double>(m);
+}
+
+// Mean Nusselt number of the x- face, Eq. (65): Nu = -(l_c / dT) <dT/dx> on
+// the wall with l_c = nx (hot-to-cold distance) and dT = <T_w> - T_m.  The
+// wall gradient is the exact lattice heat flux of the anti-bounce-back links,
+// q = -chi C_p,ref dT/dx per node and step, with chi = lambda_l / (rho0
+// C_p,ref) of the liquid at the hot wall.  NaN when the face is not a
+// fixed-temperature face or dT = 0.
+double hot_wall_nusselt(const lbpc_config& c, double inflow, double tw_mean) {
+  const double dT = tw_mean - c.T_m;
+  if (c.face_bc[0] != LBPC_DIRICHLET || dT == 0.0) return std::nan("");
+  const double q = inflow / (static_cast<double>(c.ny) * c.nz);
+  const double chi = c.lambda_l / (c.rho0 * c.cp_ref);
+  return q * c.nx / (chi * c.cp_ref * dT);
 }
 
 int read_status(lbpc_ctx* x, std::vector<int32_t>& st) {
@@ -721,10 +776,12 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
     return cleanup(fail(nullptr, LBPC_EHIP, "hipStreamCreate failed"));
   // wall fields start at the constant face temperatures
   std::vector<double> tw(static_cast<size_t>(L.tw_doubles));
+  x->tw_mean.resize(batch);
   for (int i = 0; i < batch; ++i)
     for (int f = 0; f < 6; ++f) {
       const int64_t o = L.tw_off[i] + L.twface[i][f];
       std::fill(tw.begin() + o, tw.begin() + o + face_size(cfgs[i], f), cfgs[i].face_T[f]);
+      x->tw_mean[i][f] = cfgs[i].face_T[f];
     }
   if (hipMemcpyAsync(x->d_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice,
                      x->stream) != hipSuccess ||
@@ -762,8 +819,15 @@ int lbpc_set_wall_T(lbpc_ctx* x, int32_t cavity, int32_t face, const double* dev
   if (x->cfg[cavity].face_bc[face] != LBPC_DIRICHLET)
     return fail(x, LBPC_EINVAL, "face is not a fixed-temperature face");
   double* dst = x->d_tw + x->L.tw_off[cavity] + x->L.twface[cavity][face];
-  HIPCHK(x, hipMemcpyAsync(dst, dev_Tw, sizeof(double) * face_size(x->cfg[cavity], face),
-                           hipMemcpyDeviceToDevice, x->stream));
+  const int64_t nodes = face_size(x->cfg[cavity], face);
+  HIPCHK(x, hipMemcpyAsync(dst, dev_Tw, sizeof(double) * nodes, hipMemcpyDeviceToDevice,
+                           x->stream));
+  // the face mean enters the Nusselt number of lbpc_budgets
+  std::vector<double> h(static_cast<size_t>(nodes));
+  HIPCHK(x, hipMemcpyAsync(h.data(), dev_Tw, sizeof(double) * nodes, hipMemcpyDeviceToHost,
+                           x->stream));
+  HIPCHK(x, hipStreamSynchronize(x->stream));
+  x->tw_mean[cavity][face] = face_mean(h.data(), nodes);
   return LBPC_OK;
 }
 
@@ -802,12 +866,14 @@ int lbpc_budgets(lbpc_ctx* x, double* host_out) {
                            hipMemcpyDeviceToHost, x->stream));
   HIPCHK(x, hipStreamSynchronize(x->stream));
   for (int i = 0; i < x->L.batch; ++i) {
-    host_out[6 * i + 0] = rec[i].now_H;
-    host_out[6 * i + 1] = rec[i].now_mass;
-    host_out[6 * i + 2] = rec[i].now_fl;
-    host_out[6 * i + 3] = rec[i].flux_cum;
-    host_out[6 * i + 4] = static_cast<double>(x->steps);
-    host_out[6 * i + 5] = rec[i].now_flux0;
+    double* o = host_out + kBudgetValues * i;
+    o[0] = rec[i].now_H;
+    o[1] = rec[i].now_mass;
+    o[2] = rec[i].now_fl;
+    o[3] = rec[i].flux_cum;
+    o[4] = static_cast<double>(x->steps);
+    o[5] = rec[i].now_flux0;
+    o[6] = hot_wall_nusselt(x->cfg[i], rec[i].now_flux0, x->tw_mean[i][0]);
   }
   std::vector<int32_t> st;
   return read_status(x, st);
@@ -907,6 +973,13 @@ int lbpc_load(lbpc_ctx* x, const void* host_buf, size_t bytes) {
   p += sizeof(int32_t) * x->L.batch;
   HIPCHK(x, hipMemcpyAsync(x->d_tw, p, sizeof(double) * x->L.tw_doubles, hipMemcpyHostToDevice, x->stream));
   HIPCHK(x, hipStreamSynchronize(x->stream));
+  std::vector<double> tw(static_cast<size_t>(x->L.tw_doubles));
+  std::memcpy(tw.data(), p, sizeof(double) * tw.size());
+  for (int i = 0; i < x->L.batch; ++i)
+    for (int f = 0; f < 6; ++f) {
+      const int64_t o = x->L.tw_off[i] + x->L.twface[i][f];
+      x->tw_mean[i][f] = face_mean(tw.data() + o, face_size(x->cfg[i], f));
+    }
   x->steps = hdr[3];
   x->unstable = false;
   x->adj.ready = false;

@@ -9,17 +9,30 @@ import workloads as W
 W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 
 
+def _np(a):
+    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+
+
 def rel(a, b):
-    """max |a - b| / max |b| (relative to the field's scale)."""
-    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
-    b = b.detach().cpu().numpy() if hasattr(b, "detach") else np.asarray(b)
+    """Largest relative difference.  Population arrays ([q][z][y][x], q = 7 or
+    19) are compared plane by plane, each against its own largest value, so
+    that the small moving populations are held to the same relative bound as
+    the large rest populations; other arrays against their largest value."""
+    a, b = _np(a), _np(b)
+    if a.ndim == 4 and a.shape[0] in (7, 19):
+        return max(rel(a[q], b[q]) for q in range(a.shape[0]))
     scale = np.abs(b).max()
     return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
 
 
+def plane_scales(b):
+    """Largest |value| of every population plane (diagnostics)."""
+    b = _np(b)
+    return [float(np.abs(b[q]).max()) for q in range(b.shape[0])]
+
+
 def absdiff(a, b):
-    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
-    b = b.detach().cpu().numpy() if hasattr(b, "detach") else np.asarray(b)
+    a, b = _np(a), _np(b)
     return float(np.abs(a - b).max())
 
 

@@ -135,14 +135,52 @@ def test_autograd_function_matches_adjoint():
     assert np.allclose(2.5 * g1, cav.face_slice(dtw, 0).cpu().numpy(), rtol=1e-14, atol=0)
 
 
+def _branch_codes(cav, cfg, eps):
+    """Branch of Eq. (2) that every cell of the current state takes: 0 solid,
+    1 mushy, 2 liquid, and 3 / 4 within eps of the kinks h_s / h_l."""
+    import torch
+    h = cav.fields(names=("h",))["h"]
+    hs = cfg["cp_s"] * cfg["T_m"]
+    hl = cfg["cp_l"] * cfg["T_m"] + cfg["latent"]
+    code = torch.ones_like(h, dtype=torch.int8)
+    code = torch.where(h < hs - eps, torch.zeros_like(code), code)
+    code = torch.where(h > hl + eps, torch.full_like(code, 2), code)
+    code = torch.where((h - hs).abs() <= eps, torch.full_like(code, 3), code)
+    code = torch.where((h - hl).abs() <= eps, torch.full_like(code, 4), code)
+    return code
+
+
+def _run_with_branches(cav, cfg, nsteps, eps, base=None):
+    """Step one at a time; return the loss (sum f_l at the end) and either the
+    branch pattern of every state t = 0..nsteps (base None) or the number of
+    cell-steps whose branch differs from base."""
+    import torch
+    pattern, mism = [], torch.zeros((), dtype=torch.int64, device="cuda")
+    for t in range(nsteps + 1):
+        if t:
+            cav.step(1)
+        code = _branch_codes(cav, cfg, eps)
+        if base is None:
+            pattern.append(code)
+        else:
+            mism += (code != base[t]).sum()
+    loss = cav.budgets()[0, 2]
+    return loss, (pattern if base is None else int(mism.item()))
+
+
 def test_adjoint96_fd_check_full_size():
     """Differentiation workload at full size: 96^3, Ra = 1e4, Pr = 1, Ste = 0.1,
     2000 FP64 steps, checkpoint every 100, hot wall 1 +- 0.05 (seed 1703).  The
     adjoint gradient on 16 wall nodes (seed 2652) against central differences
-    (delta = 1e-4) of the GPU FP64 forward run."""
+    (delta = 1e-4) of the GPU FP64 forward run, within 1e-6 relative.  The
+    difference quotient is a derivative only where the base, +delta and -delta
+    runs take the same branch of Eq. (2) in every cell at every step (cells
+    within 1e-12 L of a kink in all three runs excepted): nodes whose runs
+    differ anywhere are left out, and most nodes must pass that guard."""
     import torch
     n, nsteps = 96, 2000
     cfg = W.adjoint_cavity(n, precision=W.FP64)
+    eps = 1e-12 * cfg["latent"]
     Tw = W.hot_wall_field(n, n)
     nodes = W.fd_nodes(n, n)
     cav = make_cavity(cfg, walls={0: Tw})
@@ -151,23 +189,31 @@ def test_adjoint96_fd_check_full_size():
     L = cav.adjoint_forward(nsteps, 100)
     dtw, _ = cav.adjoint_backward()
     g = cav.face_slice(dtw, 0).cpu().numpy().reshape(-1)[nodes]
+    cav.load(init)
+    L0, base = _run_with_branches(cav, cfg, nsteps, eps)
+    assert L0 == pytest.approx(L, rel=1e-14)
     delta = 1e-4
-    fd = []
+    fd, ok = [], []
     for node in nodes:
-        vals = []
+        vals, same = [], True
         for sgn in (1.0, -1.0):
             cav.load(init)
             t = Tw.copy().reshape(-1)
             t[node] += sgn * delta
             cav.set_wall_T(0, t.reshape(Tw.shape))
-            cav.step(nsteps)
-            vals.append(cav.budgets()[0, 2])
+            v, mism = _run_with_branches(cav, cfg, nsteps, eps, base=base)
+            vals.append(v)
+            same = same and mism == 0
         fd.append((vals[0] - vals[1]) / (2 * delta))
-    fd = np.array(fd)
+        ok.append(same)
+    del base
+    torch.cuda.empty_cache()
+    fd, ok = np.array(fd), np.array(ok)
     err = np.abs(g - fd) / np.abs(fd)
-    print(f"96^3 L={L:.4f}; adjoint {g[:4]}; fd {fd[:4]}; max rel err {err.max():.2e}")
-    torch.cuda.synchronize()
-    assert err.max() < 1e-5
+    print(f"96^3 L={L:.4f}; adjoint {g[:4]}; fd {fd[:4]}; {ok.sum()} of {ok.size} nodes keep "
+          f"every branch; max rel err there {err[ok].max():.2e} (all nodes {err.max():.2e})")
+    assert ok.sum() >= ok.size // 2
+    assert err[ok].max() < 1e-6
 
 
 def test_adjoint_with_a_snapshot_of_every_step_equals_segments():

@@ -124,6 +124,50 @@ def test_coupled_melting_cavity_fp64():
     assert np.abs(rf["uz"]).max() > 1e-5
 
 
+@pytest.mark.parametrize("n", [32, 64])
+def test_coupled_cavity_fp64_500_steps(n):
+    """Coupled melting cavity at the headline parameters (Ra 1e5, Pr 0.02,
+    Ste 0.1, Mach-0.1 scale) on 32^3 and 64^3 with a perturbed hot wall, FP64,
+    500 steps: every population plane and the fields within 1e-12 of the
+    oracle (each plane against its own scale)."""
+    cfg = W.melting_cavity(n, 1e5, 0.02, 0.1, precision=W.FP64)
+    walls = {0: W.hot_wall_field(n, n)}
+    cav = make_cavity(cfg, walls=walls)
+    cav.step(500)
+    f, g = cav.state()
+    ref = oracle.run(cfg, oracle.init_state(cfg), 500, tw=W.wall_fields(cfg, walls))
+    ef, eg = rel(f, ref[0]), rel(g, ref[1])
+    print(f"coupled {n}^3 FP64 500 steps: rel f {ef:.2e} g {eg:.2e}")
+    assert eg < FP64_TOL and ef < FP64_TOL
+    fl = cav.fields(names=("T", "fl", "u"))
+    rf = oracle.fields(cfg, ref)
+    assert absdiff(fl["fl"], rf["fl"]) < FP64_TOL
+    assert rel(fl["T"], rf["T"]) < FP64_TOL
+    for k in ("ux", "uy", "uz"):
+        assert rel(fl[k], rf[k]) < 1e-10, k
+    assert rf["fl"].sum() > n * n
+
+
+def test_coupled_cavity_fp32_64_cubed_2000_steps_liquid_fraction():
+    """FP32 storage and arithmetic on the headline parameters (Ra 1e5, Pr 0.02,
+    Ste 0.1) at 64^3, 2000 steps: every cell's liquid fraction within 1e-5 of
+    the FP64 oracle's."""
+    cfg64 = W.melting_cavity(64, 1e5, 0.02, 0.1, precision=W.FP64)
+    cav = make_cavity(dict(cfg64, precision=W.FP32))
+    cav.step(2000)
+    fl = cav.fields(names=("T", "fl", "u"))
+    ref = oracle.run(cfg64, oracle.init_state(cfg64), 2000)
+    rf = oracle.fields(cfg64, ref)
+    err = absdiff(fl["fl"], rf["fl"])
+    umax = max(np.abs(rf[k]).max() for k in ("ux", "uy", "uz"))
+    eu = max(absdiff(fl[k], rf[k]) for k in ("ux", "uy", "uz"))
+    print(f"fp32 64^3 2000 steps: max |dfl| {err:.2e}, max |dT| {absdiff(fl['T'], rf['T']):.2e}, "
+          f"max |du| {eu:.2e} of {umax:.2e}")
+    assert err < FP32_FL_TOL
+    assert rf["fl"].sum() > 64 * 64 * 2
+    assert umax > 1e-4
+
+
 def test_coupled_melting_cavity_fp32_liquid_fraction():
     """FP32 storage and arithmetic, 32^3 cavity at Ra = 1e5, 600 steps: liquid
     fraction within 1e-5 of the FP64 oracle."""
@@ -219,6 +263,14 @@ def test_two_phase_solidification_fp64(case):
     # FP64 rounding paths drift apart linearly (tests/test_oracle_conditioning.py)
     from test_oracle_conditioning import DRIFT_PER_1000
     assert rel(g, ref[1]) < DRIFT_PER_1000 * 6
+    # the step map itself at the end of the run: one oracle step from the GPU
+    # state equals the GPU's next step to 1e-12
+    st = (None, g.cpu().numpy())
+    cav.step(1)
+    _, g1 = cav.state()
+    one = oracle.run(cfg, st, 1)
+    print(f"solidification ({case}): one step from the GPU state, rel g {rel(g1, one[1]):.2e}")
+    assert rel(g1, one[1]) < FP64_TOL
 
 
 @pytest.mark.parametrize("model", [W.SRT, W.MRT])
@@ -243,10 +295,15 @@ def test_hot_wall_flux_matches_oracle_inflow():
     tw = W.wall_fields(cfg, walls)
     cav = make_cavity(cfg, walls=walls)
     cav.step(37)
-    q = cav.budgets()[0, 5]
+    b = cav.budgets()[0]
     st = oracle.run(cfg, oracle.init_state(cfg), 37, tw=tw)
     _, hist = oracle.run(cfg, st, 1, tw=tw, history=True)
-    assert q == pytest.approx(hist[0, 3], rel=1e-12)
+    assert b[5] == pytest.approx(hist[0, 3], rel=1e-12)
+    # the library's Nusselt number, Eq. (65), against the oracle's inflow
+    chi = cfg["lambda_l"] / (cfg["rho0"] * cfg["cp_ref"])
+    dT = walls[0].mean() - cfg["T_m"]
+    nu_ref = hist[0, 3] / (14 * 14) * 14 / (chi * cfg["cp_ref"] * dT)
+    assert b[6] == pytest.approx(nu_ref, rel=1e-12)
 
 
 def test_conduction_nusselt_is_one():
@@ -263,3 +320,39 @@ def test_conduction_nusselt_is_one():
     nu = cav.nusselt()
     print("conduction Nu", nu)
     assert nu == pytest.approx(1.0, abs=1e-9)
+
+
+def test_table2_case1_full_size_one_step_and_nusselt():
+    """Table 2 case 1 on its printed grid (160 x 160 x 80, Ra 2.5e4, Pr 0.02,
+    Ste 0.4), FP32, in the launch shape the benchmark tunes: after 300 steps
+    the oracle's FP64 step from the GPU state agrees with the GPU's next state
+    to the storage rounding, and the library's hot-wall Nusselt number equals
+    Eq. (65) applied to the oracle's x- inflow of that step."""
+    cfg = W.table2_case(1)
+    cav = make_cavity(cfg)
+    cav.autotune(3)
+    cav.step(300)
+    b = cav.budgets()[0]
+    f, g = cav.state()
+    st = (f.cpu().numpy(), g.cpu().numpy())
+    del f, g
+    cav.step(1)
+    f1, g1 = cav.state()
+    cfg64 = dict(cfg, precision=W.FP64)
+    ref = oracle.run(cfg64, st, 1)
+    dev = np.abs(ref[0] - W19.reshape(19, 1, 1, 1) * cfg["rho0"]).max()
+    ef, eg = absdiff(f1, ref[0]), absdiff(g1, ref[1])
+    print(f"table 2 case 1 one step (launch {cav.get_launch()}): max|df| {ef:.2e} "
+          f"(max deviation {dev:.2e}), max|dg| {eg:.2e}")
+    assert ef < 2.0 ** -20 * dev + 1e-13
+    assert eg < 2.0 ** -20 * np.abs(ref[1][1:]).max()
+    # x- inflow alone: the same step with the cold face adiabatic (the
+    # collision is local, so the x- links see the same post-collision state)
+    one_face = dict(cfg64, face_bc=[W.DIRICHLET] + [W.ADIABATIC] * 5)
+    _, hist = oracle.run(one_face, st, 1, history=True)
+    chi = cfg["lambda_l"] / (cfg["rho0"] * cfg["cp_ref"])
+    nu_ref = hist[0, 3] / (cfg["ny"] * cfg["nz"]) * cfg["nx"] / (
+        chi * cfg["cp_ref"] * (cfg["face_T"][0] - cfg["T_m"]))
+    print(f"table 2 case 1: Nu library {b[6]:.6f}, from the oracle inflow {nu_ref:.6f}")
+    assert b[6] == pytest.approx(nu_ref, rel=1e-5)
+    assert b[6] > 1.0

@@ -99,6 +99,58 @@ def test_graph_replays_match_eager_steps_every_replay():
         assert bg[0, 4] == 16 * (replay + 1)
 
 
+def test_graph_remainders_and_pending_partials_match_eager_steps():
+    """Five eager steps leave partials in the ring; 20 more steps then reduce
+    them and run as a 16-step and a 4-step graph.  State and budgets equal 25
+    steps launched one by one, bit for bit, and the same again after 13 more
+    (a 12-step graph and one eager step)."""
+    cfg = W.melting_cavity(24, 1e5, 0.02, 0.1, precision=W.FP32)
+    cfg.update(ny=17, nz=11)
+    walls = {0: W.hot_wall_field(17, 11)}
+    g = make_cavity(cfg, walls=walls)
+    e = make_cavity(cfg, walls=walls)
+    g.set_launch(256, 0, 16, 4)
+    e.set_launch(256, 0, 0, 4)
+    for _ in range(5):
+        g.step(1)
+    g.step(20)
+    e.step(25)
+    for more in (0, 13):
+        g.step(more)
+        e.step(more)
+        bg, be = g.budgets(), e.budgets()
+        for x, y in zip(_state_bytes(g), _state_bytes(e)):
+            assert np.array_equal(x, y), more
+        assert np.array_equal(bg, be), more
+    assert bg[0, 4] == 38
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_block192_budgets_and_state_equal_block256(n):
+    """Tiles of 192 cells leave an empty wavefront at the end of the last tile
+    whenever the tile count is not a multiple of 4 (32^3, 128^3): the partial
+    arrays hold it, and state and budgets equal those of 256-cell tiles bit
+    for bit (a wave's partials do not depend on the tile size; at 32^3 one
+    reduction chunk holds every wave in both)."""
+    cfg = W.melting_cavity(n, 1e5, 0.02, 0.1, precision=W.FP32)
+    walls = {0: W.hot_wall_field(n, n)}
+    out = []
+    for block in (256, 192):
+        cav = make_cavity(cfg, walls=walls)
+        cav.set_launch(block, 0, 16, 1)
+        cav.step(37)
+        out.append((_state_bytes(cav), cav.budgets()))
+        cav.close()
+    (s256, b256), (s192, b192) = out
+    for x, y in zip(s256, s192):
+        assert np.array_equal(x, y)
+    if n == 32:
+        assert np.array_equal(b256, b192)
+    else:
+        assert np.allclose(b256, b192, rtol=1e-13, atol=0)
+    assert b192[0, 3] > 0 and b192[0, 1] == pytest.approx(n**3, rel=1e-6)
+
+
 def test_autotune_does_not_advance_state():
     cfg = W.melting_cavity(16, 1e5, 0.02, 0.1, precision=W.FP32)
     a = make_cavity(cfg)

@@ -6,14 +6,18 @@ force: two correct FP64 evaluations of the same step that round differently
 drift apart linearly in time, at the scale of ulp(L).  This test evaluates the
 D3Q7 MRT step in a second, algebraically identical FP64 form (the grouped form
 with n_4 - n_4^eq = -7 sum_{a>0} g_a + 21 omega_T C_p,ref T) and measures its
-distance to the oracle on the solidification workload with L = 250; the GPU
-parity test for that workload uses the resulting per-1000-step tolerance."""
+distance to the oracle on the solidification workload with L = 250, each
+population plane against its own largest value (the norm of the GPU parity
+tests); the GPU parity test for that workload uses the resulting
+per-1000-step tolerance.  The moving populations drift most: about 1.3e-11 of
+their scale per 1000 steps, while g_0 (of the size of L) drifts by 1.5e-12."""
 import numpy as np
 
 import oracle
 import workloads as W
+from gpu_util import rel
 
-DRIFT_PER_1000 = 2e-12
+DRIFT_PER_1000 = 2e-11
 
 
 def _grouped_step(G, n, wT=0.25, L=250.0, lam=0.4, Tw=-1.0):
@@ -55,9 +59,9 @@ def test_mushy_enthalpy_rounding_drift_is_linear_and_bounded():
             E = _grouped_step(E, n)
         st = oracle.run(cfg, st, 1000)
         R = st[1].reshape(7, n)
-        errs.append(np.abs(E - R).max() / np.abs(R).max())
+        errs.append(rel(E.reshape(7, 1, 1, n), R.reshape(7, 1, 1, n)))
     # the two FP64 forms drift apart steadily: well above 1e-12 after 6000
     # steps, yet within the stated per-1000-step bound
-    assert errs[-1] > 3e-12
+    assert errs[-1] > 3e-11
     for k, e in enumerate(errs):
         assert e < DRIFT_PER_1000 * (k + 1)
