@@ -70,7 +70,7 @@ def run_cavity(cfg, steps, warmup, launch=None, label=""):
     cav.step(warmup)
     dt = timed_steps(cav, steps)
     kern_ms = cav.time_step_kernel(20)
-    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    cells = sum(c["nx"] * c["ny"] * c["nz"] for c in (cfg if isinstance(cfg, list) else [cfg]))
     mlups = cells * steps / dt / 1e6
     log(f"[bench] {label}: {mlups:.0f} MLUPS, {1e3 * dt / steps:.4f} ms/step, kernel "
         f"{kern_ms:.4f} ms, launch {cav.get_launch()} (tuned {best})")
@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="cavity128_fp32",
                     choices=["cavity128_fp32", "cavity256_fp32", "cavity256_fp16s", "cavity256_bf16s",
-                             "cavity128_fp64"],
+                             "cavity128_fp64", "batch64_fp32"],
                     help="cavity timed for the main line (profiling of the other kernels)")
     ap.add_argument("--launch", default=None,
                     help="block,grid,graph_steps,xcd_run instead of autotuning")
@@ -323,9 +323,14 @@ def main():
         args.workload.split("_")[1]]
     if args.workload.startswith("cavity128"):
         cfg = W.cavity_128(precision=prec)
+        wl_name = "cavity128_Ra1e5_Pr0.02_Ste0.1"
+    elif args.workload.startswith("batch64"):
+        cfg, _ = W.batch_cavities(precision=prec)
+        wl_name = "batch64_N32-96_Ra1e3-1e6_Pr0.02-50_Ste0.05-0.5"
     else:
         cfg = W.precision_cavity(256, 0.02, precision=prec)
-    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+        wl_name = "cavity256_Ra1e6_Pr0.02_Ste0.1"
+    cells = sum(c["nx"] * c["ny"] * c["nz"] for c in (cfg if isinstance(cfg, list) else [cfg]))
     cav, main_r = run_cavity(cfg, args.steps, args.warmup, launch=launch, label=args.workload)
     alg_bytes = BYTES_PER_CELL[prec] * cells
     achieved = alg_bytes / (main_r["kernel_ms"] * 1e-3) / 1e9
@@ -398,7 +403,7 @@ def main():
         log(f"[bench] 2D: {extras['corner400_fp32']} {extras['convection2d128_fp32']}")
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not isinstance(cfg, list):
         cpu = cpu_baseline(dict(cfg, precision=W.FP64))
         log(f"[bench] cpu baseline: {cpu}")
         if not args.no_extras:
@@ -411,8 +416,7 @@ def main():
         warmup=args.warmup, ms_per_step=round(main_r["ms_per_step"], 5), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f64" if prec == W.FP64 else "f32",
         data="synthetic",
-        config=dict(workload=("cavity128_Ra1e5_Pr0.02_Ste0.1" if args.workload.startswith("cavity128")
-                              else "cavity256_Ra1e6_Pr0.02_Ste0.1"),
+        config=dict(workload=wl_name,
                     lattice="D3Q19 MRT + D3Q7 MRT", cells=cells,
                     storage=args.workload.split("_")[1], launch=main_r["launch"]),
         roofline=roofline, cpu_baseline=cpu, extras=extras,

