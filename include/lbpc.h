@@ -147,6 +147,21 @@ int lbpc_fields(lbpc_ctx* ctx, int32_t cavity, uint32_t mask, double* dev_out);
  * Deterministic summation order.  Synchronises the stream. */
 int lbpc_budgets(lbpc_ctx* ctx, double* host_out);
 
+/* lbpc_budgets for callers that cannot allocate device memory during the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same values into host_out[7 * cavity + k], the same
+ * kernels and summation order (so the same bits), with the per-wavefront
+ * records and chunk sums of its reductions in a static device array of
+ * 16 MiB that the library holds per device until the process ends, instead of
+ * the workspace.  It calls no allocating routine (host records go through
+ * fixed stack buffers).  The array is shared by every call on a device and
+ * keeps the last call's contents (nothing in it needs to start at zero);
+ * calls that overlap on one device, from contexts on different streams or
+ * threads, race on it.  LBPC_ENOSPACE when the batch needs more scratch than
+ * that (about 5 x 8 bytes per 64 cells: up to some 26 million cells), with
+ * the size in lbpc_last_error.  Synchronises the stream. */
+int lbpc_budgets_noalloc(lbpc_ctx* ctx, double* host_out);
+
 /* Per-cavity status bits (1 = non-finite or out-of-bound state seen; such a
  * cavity is frozen).  Synchronises the stream. */
 int lbpc_status(lbpc_ctx* ctx, int32_t* host_flags);

@@ -18,7 +18,7 @@ FIELD_BITS = {"h": 1, "T": 2, "fl": 4, "rho": 8, "u": 16}
 # every entry point declared in include/lbpc.h
 EXPORTS = (
     "lbpc_workspace_bytes", "lbpc_create", "lbpc_set_wall_T", "lbpc_step", "lbpc_fields",
-    "lbpc_budgets", "lbpc_status", "lbpc_get_state", "lbpc_set_state", "lbpc_state_bytes",
+    "lbpc_budgets", "lbpc_budgets_noalloc", "lbpc_status", "lbpc_get_state", "lbpc_set_state", "lbpc_state_bytes",
     "lbpc_save", "lbpc_load", "lbpc_set_launch", "lbpc_get_launch", "lbpc_autotune",
     "lbpc_time_step_kernel", "lbpc_adjoint_workspace_bytes", "lbpc_adjoint_forward",
     "lbpc_adjoint_backward", "lbpc_adjoint", "lbpc_destroy", "lbpc_last_error", "lbpc_version",
@@ -84,6 +84,7 @@ def lib():
     L.lbpc_step.argtypes = [vp, i64]
     L.lbpc_fields.argtypes = [vp, i32, u32, vp]
     L.lbpc_budgets.argtypes = [vp, dp]
+    L.lbpc_budgets_noalloc.argtypes = [vp, dp]
     L.lbpc_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.lbpc_get_state.argtypes = [vp, i32, vp, vp]
     L.lbpc_set_state.argtypes = [vp, i32, vp, vp]
@@ -107,6 +108,7 @@ def lib():
     L.lbpc_last_error.restype = ctypes.c_char_p
     L.lbpc_version.restype = ctypes.c_char_p
     for name in ("lbpc_create", "lbpc_set_wall_T", "lbpc_step", "lbpc_fields", "lbpc_budgets",
+                 "lbpc_budgets_noalloc",
                  "lbpc_status", "lbpc_get_state", "lbpc_set_state", "lbpc_save", "lbpc_load",
                  "lbpc_set_launch", "lbpc_get_launch", "lbpc_autotune", "lbpc_time_step_kernel",
                  "lbpc_adjoint_forward", "lbpc_adjoint_backward", "lbpc_adjoint"):

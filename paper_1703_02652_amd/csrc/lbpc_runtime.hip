@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,41 @@ __global__ void __launch_bounds__(256) k_fill_zero(uint32_t* p, int64_t nwords) 
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < nwords;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     p[i] = 0u;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of lbpc_budgets_noalloc: the chunk sums of its reductions
+// (up to kRing slots) and the per-wavefront records of its measure pass.  One
+// copy per device, held until the process ends; host code addresses it only
+// through the device address that hipGetSymbolAddress returns for the current
+// device (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +436,7 @@ struct lbpc_ctx {
   double* d_sums = nullptr;   // state sums per wavefront (full-partials steps)
   double* d_mpart = nullptr;  // measure pass records
   char* region[2] = {nullptr, nullptr};
+  char* scratch = nullptr;      // device address of the static scratch on this context's device
   int cur = 0;
   int flip = 0;                 // direction of the next step's walk of the queue
   int block = 256, grid = 0, graph_steps = 16, xrun = 4;
@@ -478,15 +515,19 @@ hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
 
 // mode 0: the steps of the ring (inflow arrays from `partials`, state sums of
 // the last one); mode 1: the measure pass (its records in `partials`).
-hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st) {
+// csum: chunk sums of up to kRing slots (the workspace's, or the static
+// scratch of lbpc_budgets_noalloc).
+hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hipStream_t st,
+                  double* csum = nullptr) {
   const int64_t csum_stride = x->L.max_chunks * NPART;
+  if (!csum) csum = x->d_csum;
   const double* flux = mode == 0 ? partials : nullptr;
   const double* sums = mode == 0 ? x->d_sums : partials;
   hipLaunchKernelGGL(k_reduce_chunks, dim3(x->nchunks, nslots), dim3(256), 0, st, x->d_chunks,
-                     flux, static_cast<int64_t>(x->L.max_waves), sums, x->d_csum, csum_stride,
+                     flux, static_cast<int64_t>(x->L.max_waves), sums, csum, csum_stride,
                      x->block / 64);
   hipLaunchKernelGGL(k_reduce_final, dim3(x->L.batch), dim3(64 * nslots), 0, st, x->d_params,
-                     x->d_csum, csum_stride, nslots, mode, x->d_rec, x->d_status);
+                     csum, csum_stride, nslots, mode, x->d_rec, x->d_status);
   return hipGetLastError();
 }
 
@@ -588,9 +629,9 @@ int build_tiles(lbpc_ctx* x) {
   return LBPC_OK;
 }
 
-int flush(lbpc_ctx* x) {
+int flush(lbpc_ctx* x, double* csum = nullptr) {
   if (x->pending > 0) {
-    HIPCHK(x, reduce(x, x->d_part, x->pending, 0, x->stream));
+    HIPCHK(x, reduce(x, x->d_part, x->pending, 0, x->stream, csum));
     x->pending = 0;
   }
   return LBPC_OK;
@@ -781,6 +822,12 @@ int lbpc_create(const lbpc_config* cfgs, int32_t batch, void* dev_workspace, siz
   };
   if (hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking) != hipSuccess)
     return cleanup(fail(nullptr, LBPC_EHIP, "hipStreamCreate failed"));
+  {
+    const hipError_t e = scratch_address(&x->scratch);
+    if (e != hipSuccess)
+      return cleanup(fail(nullptr, LBPC_EHIP, std::string("static scratch address: ") +
+                                                  hipGetErrorString(e)));
+  }
   // wall fields start at the constant face temperatures
   std::vector<double> tw(static_cast<size_t>(L.tw_doubles));
   x->tw_mean.resize(batch);
@@ -884,6 +931,53 @@ int lbpc_budgets(lbpc_ctx* x, double* host_out) {
   }
   std::vector<int32_t> st;
   return read_status(x, st);
+}
+
+int lbpc_budgets_noalloc(lbpc_ctx* x, double* host_out) {
+  if (!x || !host_out) return fail(x, LBPC_EINVAL, "null argument");
+  // scratch: [chunk sums of kRing slots][measure records], 256-byte aligned
+  const size_t csum_bytes =
+      align_up(sizeof(double) * NPART * static_cast<size_t>(x->L.max_chunks) * kRing);
+  const size_t rec_bytes = sizeof(double) * NPART * static_cast<size_t>(x->L.max_waves);
+  if (csum_bytes + rec_bytes > kScratchBytes) {
+    char msg[200];
+    std::snprintf(msg, sizeof(msg),
+                  "lbpc_budgets_noalloc: this batch needs %zu bytes of scratch, more than the "
+                  "%zu the library holds per device (use lbpc_budgets)",
+                  csum_bytes + rec_bytes, kScratchBytes);
+    return fail(x, LBPC_ENOSPACE, msg);
+  }
+  double* csum = reinterpret_cast<double*>(x->scratch);
+  double* mrec = reinterpret_cast<double*>(x->scratch + csum_bytes);
+  int rc = flush(x, csum);
+  if (rc) return rc;
+  HIPCHK(x, dispatch_measure(x, x->region[x->cur], mrec));
+  HIPCHK(x, reduce(x, mrec, 1, 1, x->stream, csum));
+  // records and status through fixed host buffers on the stack, a chunk at a time
+  constexpr int kChunkCav = 32;
+  BudgetRec rec[kChunkCav];
+  int32_t st[kChunkCav];
+  for (int i0 = 0; i0 < x->L.batch; i0 += kChunkCav) {
+    const int m = std::min(kChunkCav, x->L.batch - i0);
+    HIPCHK(x, hipMemcpyAsync(rec, x->d_rec + i0, sizeof(BudgetRec) * m, hipMemcpyDeviceToHost,
+                             x->stream));
+    HIPCHK(x, hipMemcpyAsync(st, x->d_status + i0, sizeof(int32_t) * m, hipMemcpyDeviceToHost,
+                             x->stream));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
+    for (int k = 0; k < m; ++k) {
+      const int i = i0 + k;
+      double* o = host_out + kBudgetValues * i;
+      o[0] = rec[k].now_H;
+      o[1] = rec[k].now_mass;
+      o[2] = rec[k].now_fl;
+      o[3] = rec[k].flux_cum;
+      o[4] = static_cast<double>(x->steps);
+      o[5] = rec[k].now_flux0;
+      o[6] = hot_wall_nusselt(x->cfg[i], rec[k].now_flux0, x->tw_mean[i][0]);
+      if (st[k]) x->unstable = true;
+    }
+  }
+  return LBPC_OK;
 }
 
 int lbpc_status(lbpc_ctx* x, int32_t* host_flags) {
