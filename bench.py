@@ -342,8 +342,9 @@ def main():
                     bytes_per_cell=BYTES_PER_CELL[prec], bytes_per_launch=alg_bytes,
                     format_bytes_per_cell=FORMAT_BYTES_PER_CELL[prec],
                     kernel_ms=round(main_r["kernel_ms"], 5),
-                    time_source="mean duration of the step kernel, HIP events on the library's "
-                                "stream around runs of back-to-back launches",
+                    time_source="mean duration of the step kernel: start and stop events of "
+                                "each launch (hipExtLaunchKernel) on the library's stream, over "
+                                "runs of back-to-back launches",
                     frac_of_step=round(step_gbs / HBM_PEAK_GBS, 4))
     cav.close()
     del cav

@@ -215,8 +215,9 @@ int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 
 /* Advance nsteps with eager step-kernel launches on the library's stream:
  * runs of up to 15 back-to-back wall-inflow-partials steps (the kernel the
- * graphs run) between one HIP event pair each, then one step with all
- * partials outside the timed window.  The mean time per timed step in
+ * graphs run), each launched with a start and a stop event that the runtime
+ * records at the start and the end of the kernel itself (hipExtLaunchKernel),
+ * then one step with all partials, not counted.  The mean kernel duration in
  * milliseconds goes to host_ms_out.  Synchronises. */
 int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
 

@@ -5,10 +5,14 @@
 // the post-collision populations except on fixed-temperature links, where
 // g_abar(x) = -g*_a(x) + omega_T C_p,ref T_w.  For a loss of s_T the adjoint
 // runs backwards, lambda_t = dC^T (S^T lambda_{t+1}):
-//   - S^T is a gather: the adjoint of the post-collision population a at x is
+//   - S^T: the adjoint of the post-collision population a at x is
 //     lambda_a(x + e_a) for an interior link, lambda_abar(x) for a bounce-back
 //     link and -lambda_abar(x) for an anti-bounce-back link, which also adds
-//     omega_T C_p,ref lambda_abar(x) to dL/dT_w at that wall node;
+//     omega_T C_p,ref lambda_abar(x) to dL/dT_w at that wall node.  It is
+//     applied as a push when lambda is written: each adjoint step stores
+//     M = S^T lambda_t (the transpose of the forward push is a pull, and a
+//     pull of lambda_{t+1} is a push of lambda_t), so the next adjoint step
+//     reads M aligned, as the forward step reads its state;
 //   - dC^T is the transposed Jacobian of one cell update, written out by hand
 //     below (reverse order of the forward cell update: enthalpy collision,
 //     flow collision, forces and velocity, phase rule).  The phase rule is
@@ -18,16 +22,6 @@
 #include "lbpc_device.hpp"
 
 namespace lbpc {
-
-// Cached loads for gathers, where neighbouring waves read the two parts of a
-// cache line.
-template <class S> __device__ __forceinline__ S buf_ld_gather(__amdgpu_buffer_rsrc_t r, uint32_t off);
-template <> __device__ __forceinline__ double buf_ld_gather<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(off), 0, 0));
-}
-template <> __device__ __forceinline__ float buf_ld_gather<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(off), 0, 0));
-}
 
 // Adjoint populations: planes of the compute type, 19 f planes (with flow)
 // then g_0..g_6, at the same plane stride as the state.
@@ -41,6 +35,80 @@ __device__ __forceinline__ AdjView<R> adj_view(const char* base, int64_t plane, 
   v.f = reinterpret_cast<R*>(const_cast<char*>(base));
   v.g = v.f + (flow ? 19 * plane : 0);
   return v;
+}
+
+// Store lambda_t(x) (lf: 19 flow, lg: 7 enthalpy components) as M = S^T
+// lambda_t, which the adjoint step before it reads aligned: M_a(x - e_a) =
+// lambda_a(x) for an interior link.  Where x - e_a lies outside, the link from
+// x along e_abar hits a wall and lambda_a(x) goes to M_abar(x): as it is at a
+// bounce-back or adiabatic link, negated at an anti-bounce-back link, which
+// also adds omega_T C_p,ref lambda_a(x) to dL/dT_w of that wall node (one
+// D3Q7 link crosses a face at each wall node, so one thread updates each
+// accumulator per launch; single-cavity contexts, face fields from offset 0).
+// Every slot of M is written exactly once.  natural: store lambda_t itself
+// (the last adjoint step, whose result feeds dL/dT0).
+template <class R, bool FLOW>
+__device__ __forceinline__ void store_adjoint(const CavParams& c, const Site& s, const AdjView<R>& mo,
+                                              int64_t pl, uint32_t pbr, uint32_t ocr, const R* lf,
+                                              const R* lg, double* dTw, bool natural) {
+  const uint32_t esz = static_cast<uint32_t>(sizeof(R));
+  if (natural) {
+    if (FLOW) {
+#pragma unroll
+      for (int a = 0; a < 19; ++a) buf_st<R>(plane_rsrc(mo.f + a * pl, pbr), ocr, lf[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) buf_st<R>(plane_rsrc(mo.g + a * pl, pbr), ocr, lg[a]);
+    return;
+  }
+  if (FLOW) {
+    buf_st<R>(plane_rsrc(mo.f, pbr), ocr, lf[0]);
+#pragma unroll
+    for (int a = 1; a < 19; ++a) {
+      bool wall;
+      uint32_t to;
+      if (c.walls_only) {
+        wall = hits_wall(s, -Q19X[a], -Q19Y[a], -Q19Z[a]);
+        const int32_t shift = Q19X[a] + Q19Y[a] * c.nx + Q19Z[a] * c.nxy;
+        to = ocr - static_cast<uint32_t>(shift) * esz;
+      } else {
+        int face;
+        const int32_t t = link_target(c, s, -Q19X[a], -Q19Y[a], -Q19Z[a], face);
+        wall = face >= 0;
+        to = static_cast<uint32_t>(t) * esz;
+      }
+      buf_st<R>(plane_rsrc(mo.f + a * pl, pbr), wall ? kDrop : to, lf[a]);
+      if (wall) buf_st<R>(plane_rsrc(mo.f + Q19OPP[a] * pl, pbr), ocr, lf[a]);  // bounce-back
+    }
+  }
+  buf_st<R>(plane_rsrc(mo.g, pbr), ocr, lg[0]);
+#pragma unroll
+  for (int a = 1; a < 7; ++a) {
+    const int b = Q7OPP[a];
+    int face;
+    bool wall;
+    uint32_t to;
+    if (c.walls_only) {
+      face = (b & 1) ? b : b - 2;  // face crossed along e_b: +x -> x+ (1), -x -> x- (0), ...
+      wall = hits_wall(s, -Q7X[a], -Q7Y[a], -Q7Z[a]);
+      const int32_t shift = Q7X[a] + Q7Y[a] * c.nx + Q7Z[a] * c.nxy;
+      to = ocr - static_cast<uint32_t>(shift) * esz;
+    } else {
+      const int32_t t = link_target(c, s, -Q7X[a], -Q7Y[a], -Q7Z[a], face);
+      wall = face >= 0;
+      to = static_cast<uint32_t>(t) * esz;
+    }
+    buf_st<R>(plane_rsrc(mo.g + a * pl, pbr), wall ? kDrop : to, lg[a]);
+    if (wall) {
+      if (c.bc[face] == BC_DIRICHLET) {
+        buf_st<R>(plane_rsrc(mo.g + b * pl, pbr), ocr, -lg[a]);
+        const int64_t node = c.twface[face] + face_node(c, s, face);
+        dTw[node] += c.omega_T * c.cp_ref * static_cast<double>(lg[a]);
+      } else {
+        buf_st<R>(plane_rsrc(mo.g + b * pl, pbr), ocr, lg[a]);
+      }
+    }
+  }
 }
 
 // Transposed flow collision: given lf (adjoint of f*), accumulate into lf
@@ -189,7 +257,7 @@ __device__ __forceinline__ void flow_collide_vjp(const CavParams& c, R* lf, cons
 template <int P, bool FLOW, bool MRT>
 __global__ void __launch_bounds__(256)
 k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int ntiles, int reverse,
-          const char* __restrict__ state, const char* __restrict__ lam_in,
+          int last, const char* __restrict__ state, const char* __restrict__ lam_in,
           char* __restrict__ lam_out, double* __restrict__ dTw) {
   using R = typename Fmt<P>::R;
   // consecutive adjoint steps walk the queue in opposite directions, as the
@@ -238,67 +306,15 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     const R ux = FLOW ? q.ux : R(0), uy = FLOW ? q.uy : R(0), uz = FLOW ? q.uz : R(0);
     const R sig = sigma_chi<R>(c, fl);
 
-    // ---- gather the adjoint of the post-collision populations (S^T).  With
-    // walls on all six faces an interior link's source is this cell plus a
-    // shift that is uniform per cavity; a lane whose link hits a wall loads
-    // past the plane end (the hardware returns 0) and then reads its own
-    // reflected slot.  Periodic faces take link_target.
-    const Site s = make_site(c, cell);
+    // ---- the adjoint of the post-collision populations, M = S^T lambda_{t+1},
+    // stored by the adjoint step after this one: aligned loads
     R lf[19], lg[7];
     if (FLOW) {
-      lf[0] = buf_ld_gather<R>(plane_rsrc(li.f, pbr), ocr);
 #pragma unroll
-      for (int a = 1; a < 19; ++a) {
-        bool wall;
-        uint32_t from;
-        if (c.walls_only) {
-          wall = hits_wall(s, Q19X[a], Q19Y[a], Q19Z[a]);
-          const int32_t shift = Q19X[a] + Q19Y[a] * c.nx + Q19Z[a] * c.nxy;
-          from = wall ? kDrop : ocr + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(R));
-        } else {
-          int face;
-          const int32_t to = link_target(c, s, Q19X[a], Q19Y[a], Q19Z[a], face);
-          wall = face >= 0;
-          from = wall ? kDrop : static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(R));
-        }
-        R v = buf_ld_gather<R>(plane_rsrc(li.f + a * pl, pbr), from);
-        if (wall) v = buf_ld_gather<R>(plane_rsrc(li.f + Q19OPP[a] * pl, pbr), ocr);  // bounce-back
-        lf[a] = v;
-      }
+      for (int a = 0; a < 19; ++a) lf[a] = buf_ld<R>(plane_rsrc(li.f + a * pl, pbr), ocr);
     }
-    lg[0] = buf_ld_gather<R>(plane_rsrc(li.g, pbr), ocr);
 #pragma unroll
-    for (int a = 1; a < 7; ++a) {
-      int face;
-      bool wall;
-      uint32_t from;
-      if (c.walls_only) {
-        face = (a & 1) ? a : a - 2;  // +x -> x+ face (1), -x -> x- face (0), ...
-        wall = hits_wall(s, Q7X[a], Q7Y[a], Q7Z[a]);
-        const int32_t shift = Q7X[a] + Q7Y[a] * c.nx + Q7Z[a] * c.nxy;
-        from = wall ? kDrop : ocr + static_cast<uint32_t>(shift) * static_cast<uint32_t>(sizeof(R));
-      } else {
-        const int32_t to = link_target(c, s, Q7X[a], Q7Y[a], Q7Z[a], face);
-        wall = face >= 0;
-        from = wall ? kDrop : static_cast<uint32_t>(to) * static_cast<uint32_t>(sizeof(R));
-      }
-      R v = buf_ld_gather<R>(plane_rsrc(li.g + a * pl, pbr), from);
-      if (wall) {
-        const R back = buf_ld_gather<R>(plane_rsrc(li.g + Q7OPP[a] * pl, pbr), ocr);
-        if (c.bc[face] == BC_DIRICHLET) {
-          v = -back;
-          // one D3Q7 link crosses a face at each wall node, so one thread
-          // writes each accumulator per launch (no atomics needed); the
-          // adjoint runs on single-cavity contexts, whose face fields start
-          // at offset 0
-          const int64_t node = c.twface[face] + face_node(c, s, face);
-          dTw[node] += c.omega_T * c.cp_ref * static_cast<double>(back);
-        } else {
-          v = back;
-        }
-      }
-      lg[a] = v;
-    }
+    for (int a = 0; a < 7; ++a) lg[a] = buf_ld<R>(plane_rsrc(li.g + a * pl, pbr), ocr);
 
     // ---- transposed enthalpy collision
     R Tb = 0, flb = 0, cpb = 0, sigb = 0, s6b = 0, uxb = 0, uyb = 0, uzb = 0;
@@ -405,22 +421,25 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         if (Q19X[a] != 0) v += Q19X[a] > 0 ? jxb : -jxb;
         if (Q19Y[a] != 0) v += Q19Y[a] > 0 ? jyb : -jyb;
         if (Q19Z[a] != 0) v += Q19Z[a] > 0 ? jz0b : -jz0b;
-        buf_st<R>(plane_rsrc(lo.f + a * pl, pbr), ocr, v);
+        lf[a] = v;
       }
     }
     // ---- phase rule and h = sum g
     const R hb = Tb * dT_dh + flb * dfl_dh;
-    buf_st<R>(plane_rsrc(lo.g, pbr), ocr, lgo[0] + hb);
+    lgo[0] = lgo[0] + hb;
 #pragma unroll
-    for (int a = 1; a < 7; ++a) buf_st<R>(plane_rsrc(lo.g + a * pl, pbr), ocr, lgo[a] + hb + s6b);
+    for (int a = 1; a < 7; ++a) lgo[a] = lgo[a] + hb + s6b;
+    store_adjoint<R, FLOW>(c, make_site(c, cell), lo, pl, pbr, ocr, lf, lgo, dTw, last != 0);
   }
 }
 
-// Adjoint of the loss at the final state: lambda_g = seed dL/dh, lambda_f = 0.
+// Adjoint of the loss at the final state, lambda_g = seed dL/dh and
+// lambda_f = 0, stored as M = S^T lambda_T for the last forward step (with
+// its dL/dT_w contributions).
 template <int P, bool FLOW>
 __global__ void __launch_bounds__(256)
 k_adj_seed(const CavParams* __restrict__ cavp, const char* __restrict__ state,
-           char* __restrict__ lam, double scale) {
+           char* __restrict__ lam, double scale, double* __restrict__ dTw) {
   using R = typename Fmt<P>::R;
   const CavParams& c = *cavp;
   const int32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -434,12 +453,14 @@ k_adj_seed(const CavParams* __restrict__ cavp, const char* __restrict__ state,
   const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(moving_sum(g));
   const double dfl = (h > c.hs && h < c.hl) ? c.inv_dh : 0.0;
   const R v = static_cast<R>(scale * dfl);
+  R lf[19], lg[7];
 #pragma unroll
-  for (int a = 0; a < 7; ++a) lv.g[a * pl + cell] = v;
-  if (FLOW) {
+  for (int a = 0; a < 19; ++a) lf[a] = 0;
 #pragma unroll
-    for (int a = 0; a < 19; ++a) lv.f[a * pl + cell] = 0;
-  }
+  for (int a = 0; a < 7; ++a) lg[a] = v;
+  const uint32_t pbr = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(R));
+  const uint32_t ocr = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(R));
+  store_adjoint<R, FLOW>(c, make_site(c, cell), lv, pl, pbr, ocr, lf, lg, dTw, false);
 }
 
 // dL/dT0 from the adjoint of the initial state made by k_init: g_0 = h0 -

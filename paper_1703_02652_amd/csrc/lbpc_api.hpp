@@ -88,6 +88,9 @@ struct StepArgs {
   int reverse;                  // 1: walk each XCD's queue positions from their end
   int flow, mrt;
   hipStream_t stream;
+  // non-null: timing events recorded at the start and the end of the kernel
+  // itself (hipExtLaunchKernel), for the kernel-duration timer
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 struct AdjArgs {
@@ -95,11 +98,12 @@ struct AdjArgs {
   const int2* tiles;
   int ntiles;
   const char* state;            // state at t (storage format)
-  const char* lam_in;           // adjoint of the state at t+1 (compute format)
-  char* lam_out;                // adjoint of the state at t
+  const char* lam_in;           // S^T lambda_{t+1}, stored by the step before (compute format)
+  char* lam_out;                // S^T lambda_t (lambda_0 itself when last)
   double* dTw;                  // wall-temperature gradient accumulators (per cavity block)
   int block;
   int reverse;                  // 1: walk each XCD's queue positions from their end
+  int last;                     // 1: the step to time 0 (stores lambda_0 itself, no dT_w terms)
   int flow, mrt;
   hipStream_t stream;
 };
@@ -124,7 +128,7 @@ template <int P> hipError_t launch_set_state(const CavParams* cav, int64_t n, in
 template <int P> hipError_t launch_adjoint(const AdjArgs& a);
 template <int P> hipError_t launch_adj_seed(const CavParams* cav, int64_t n, int flow,
                                             double scale, const char* state, char* lam,
-                                            hipStream_t st);
+                                            double* dTw, hipStream_t st);
 template <int P> hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int flow,
                                           const char* state0, const char* lam, double* out,
                                           hipStream_t st);

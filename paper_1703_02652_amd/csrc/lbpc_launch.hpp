@@ -1,6 +1,8 @@
 // Host-side launchers of the per-format kernels.  Each kernel translation unit
 // includes this file once and instantiates the launchers for one format.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "lbpc_adjoint.hpp"
 #include "lbpc_device.hpp"
 
@@ -22,9 +24,16 @@ hipError_t launch_step(const StepArgs& a) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 grid(step_grid(a.ntiles, a.grid));
   const dim3 block(a.block);
-#define LBPC_STEP(FL, MR, BU)                                                              \
-  hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
-                     a.ntiles, a.reverse, a.src, a.dst, a.partials, a.sums, a.status)
+#define LBPC_STEP(FL, MR, BU)                                                                  \
+  do {                                                                                         \
+    if (a.ev_start)                                                                            \
+      hipExtLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.ev_start,     \
+                            a.ev_stop, 0, a.cavs, a.tiles, a.ntiles, a.reverse, a.src, a.dst,  \
+                            a.partials, a.sums, a.status);                                     \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
+                         a.ntiles, a.reverse, a.src, a.dst, a.partials, a.sums, a.status);     \
+  } while (0)
 #define LBPC_STEP_B(FL, MR)                                    \
   do {                                                         \
     if (a.budget == 2) LBPC_STEP(FL, MR, 2);                   \
@@ -92,7 +101,7 @@ hipError_t launch_adjoint(const AdjArgs& a) {
   const dim3 grid(step_grid(a.ntiles, 0)), block(a.block);
 #define LBPC_ADJ(FL, MR)                                                                    \
   hipLaunchKernelGGL((k_adjoint<P, FL, MR>), grid, block, 0, a.stream, a.cavs, a.tiles,    \
-                     a.ntiles, a.reverse, a.state, a.lam_in, a.lam_out, a.dTw)
+                     a.ntiles, a.reverse, a.last, a.state, a.lam_in, a.lam_out, a.dTw)
   if (a.flow) { if (a.mrt) LBPC_ADJ(true, true); else LBPC_ADJ(true, false); }
   else { if (a.mrt) LBPC_ADJ(false, true); else LBPC_ADJ(false, false); }
 #undef LBPC_ADJ
@@ -101,9 +110,9 @@ hipError_t launch_adjoint(const AdjArgs& a) {
 
 template <int P>
 hipError_t launch_adj_seed(const CavParams* cav, int64_t n, int flow, double scale,
-                           const char* state, char* lam, hipStream_t st) {
-  if (flow) hipLaunchKernelGGL((k_adj_seed<P, true>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale);
-  else hipLaunchKernelGGL((k_adj_seed<P, false>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale);
+                           const char* state, char* lam, double* dTw, hipStream_t st) {
+  if (flow) hipLaunchKernelGGL((k_adj_seed<P, true>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale, dTw);
+  else hipLaunchKernelGGL((k_adj_seed<P, false>), cell_grid(n), dim3(256), 0, st, cav, state, lam, scale, dTw);
   return hipGetLastError();
 }
 
@@ -129,7 +138,7 @@ hipError_t launch_adj_T0(const CavParams* cav, int64_t n, int flow, const char* 
                                           const double*, hipStream_t);                            \
   template hipError_t launch_adjoint<P>(const AdjArgs&);                                          \
   template hipError_t launch_adj_seed<P>(const CavParams*, int64_t, int, double, const char*,     \
-                                         char*, hipStream_t);                                     \
+                                         char*, double*, hipStream_t);                            \
   template hipError_t launch_adj_T0<P>(const CavParams*, int64_t, int, const char*, const char*,  \
                                        double*, hipStream_t);
 

@@ -467,8 +467,11 @@ int fail(lbpc_ctx* x, int code, const std::string& msg) {
   } while (0)
 
 hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials, int budget,
-                         hipStream_t st) {
+                         hipStream_t st, hipEvent_t ev_start = nullptr,
+                         hipEvent_t ev_stop = nullptr) {
   StepArgs a;
+  a.ev_start = ev_start;
+  a.ev_stop = ev_stop;
   a.sums = x->d_sums;
   a.cavs = x->d_params;
   a.tiles = x->d_tiles;
@@ -1125,17 +1128,22 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   if (!x || nsteps < 1) return fail(x, LBPC_EINVAL, "bad argument");
   int rc = flush(x);
   if (rc) return rc;
-  // Runs of back-to-back wall-inflow-partials steps (the kernel the graphs run)
-  // between one event pair each; the step that closes a reduction carries all
-  // partials and runs outside the timed window.  Per-kernel completion events
-  // would add their own release to every measured kernel.
-  EventPair ev;
-  HIPCHK(x, ev.create());
-  hipEvent_t e0 = ev.e0, e1 = ev.e1;
-  auto one_step = [&](int budget) -> hipError_t {
+  // Runs of back-to-back wall-inflow-partials steps (the kernel the graphs
+  // run), each launched with a start and a stop event that the runtime records
+  // at the start and the end of the kernel itself; the step that closes a
+  // reduction carries all partials and is not counted.
+  struct Events {
+    hipEvent_t e[2 * kRing] = {};
+    ~Events() {
+      for (hipEvent_t v : e)
+        if (v) (void)hipEventDestroy(v);
+    }
+  } ev;
+  for (hipEvent_t& v : ev.e) HIPCHK(x, hipEventCreate(&v));
+  auto one_step = [&](int budget, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
     double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
-    const hipError_t e =
-        dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget, x->stream);
+    const hipError_t e = dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget,
+                                       x->stream, e0, e1);
     x->cur ^= 1;
     x->steps += 1;
     x->pending += 1;
@@ -1145,21 +1153,16 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   int64_t counted = 0, left = nsteps;
   while (left > 0) {
     const int k = static_cast<int>(std::min<int64_t>(left - 1, kRing - 1));
+    for (int i = 0; i < k; ++i) HIPCHK(x, one_step(1, ev.e[2 * i], ev.e[2 * i + 1]));
+    HIPCHK(x, one_step(2, ev.e[2 * kRing - 2], ev.e[2 * kRing - 1]));
+    HIPCHK(x, hipStreamSynchronize(x->stream));
     float ms = 0.f;
-    if (k > 0) {
-      HIPCHK(x, hipEventRecord(e0, x->stream));
-      for (int i = 0; i < k; ++i) HIPCHK(x, one_step(1));
-      HIPCHK(x, hipEventRecord(e1, x->stream));
-      HIPCHK(x, hipEventSynchronize(e1));
-      HIPCHK(x, hipEventElapsedTime(&ms, e0, e1));
+    for (int i = 0; i < k; ++i) {
+      HIPCHK(x, hipEventElapsedTime(&ms, ev.e[2 * i], ev.e[2 * i + 1]));
       total += ms;
-      counted += k;
     }
-    HIPCHK(x, hipEventRecord(e0, x->stream));
-    HIPCHK(x, one_step(2));
-    HIPCHK(x, hipEventRecord(e1, x->stream));
-    HIPCHK(x, hipEventSynchronize(e1));
-    HIPCHK(x, hipEventElapsedTime(&ms, e0, e1));
+    counted += k;
+    HIPCHK(x, hipEventElapsedTime(&ms, ev.e[2 * kRing - 2], ev.e[2 * kRing - 1]));
     single = ms;
     left -= k + 1;
     rc = flush(x);
@@ -1377,9 +1380,10 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
   const double area = static_cast<double>(x->cfg[0].ny) * x->cfg[0].nz;
   const double scale = a.loss == 0 ? seed : seed / area;
   const int prec = x->L.prec, flow = x->L.flow;
-  HIPCHK(x, prec == 0 ? launch_adj_seed<0>(cp, n, flow, scale, x->region[x->cur], lam[0], x->stream)
-                      : launch_adj_seed<1>(cp, n, flow, scale, x->region[x->cur], lam[0], x->stream));
-  int li = 0;  // lam[li] holds the adjoint of the state at the current time
+  // the seed stores S^T lambda_T, with the dL/dT_w terms of the last step
+  HIPCHK(x, prec == 0 ? launch_adj_seed<0>(cp, n, flow, scale, x->region[x->cur], lam[0], dtw, x->stream)
+                      : launch_adj_seed<1>(cp, n, flow, scale, x->region[x->cur], lam[0], dtw, x->stream));
+  int li = 0;  // lam[li] holds S^T lambda at the current time (lambda_0 itself at the end)
   auto state_at = [&](int64_t t, int64_t t0) -> char* {
     const int64_t seg = t0 / a.every;
     if (t == t0) return a.ws + a.o_snap + rb * static_cast<size_t>(seg);
@@ -1402,6 +1406,7 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
       g.dTw = dtw;
       g.block = x->block;
       g.reverse = li;  // alternates from one adjoint step to the next
+      g.last = t == 0;
       g.flow = flow;
       g.mrt = x->L.mrt;
       g.stream = x->stream;
