@@ -229,6 +229,52 @@ def adjoint_ratio(prec, n=96, steps=2000, every=100):
                 total_over_forward=(t2 - t0) / t_fwd)
 
 
+def table2_history(case=1, fo_end=0.8, samples=8):
+    """Sec. 3.3, Table 2 case 1 (160 x 160 x 80, Ra 2.5e4, Pr 0.02, Ste 0.4,
+    FP32) run to Fo = 0.8, as the paper's Fig. 12 shows it: the library's
+    hot-wall Nusselt number (Eq. (65)) and the mean liquid fraction at eight
+    Fourier numbers.  The paper's curves are figures, so this is a record of
+    the run, not a comparison."""
+    import workloads as W
+    from paper_1703_02652_amd import Cavity
+    cfg = W.table2_case(case, precision=W.FP32)
+    n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    chi = cfg["lambda_l"] / (cfg["rho0"] * cfg["cp_ref"])
+    lc = cfg["nx"]
+    cav = Cavity(cfg, device="cuda")
+    cav.autotune(5)
+    rows, done, t_run = [], 0, 0.0
+    for k in range(1, samples + 1):
+        target = int(round(fo_end * k / samples * lc * lc / chi))
+        t_run += timed_steps(cav, target - done)
+        done = target
+        b = cav.budgets()
+        rows.append(dict(fo=round(chi * done / lc ** 2, 4), steps=done,
+                         nusselt=round(float(b[0, 6]), 4), mean_fl=round(float(b[0, 2]) / n, 6)))
+    r = dict(case=case, cells=n, steps=done, mlups=round(n * done / t_run / 1e6, 1),
+             launch=list(cav.get_launch()), unstable=int(cav.status().max()), history=rows)
+    cav.close()
+    return r
+
+
+def adjoint_line(args):
+    """The differentiation workload (96^3, Ra 1e4, Pr 1, Ste 0.1, checkpoint
+    every 100 steps) over --steps steps as the main line: backward / forward
+    time per step, with the adjoint kernel's roofline."""
+    import workloads as W
+    prec = W.FP32 if args.workload.endswith("fp32") else W.FP64
+    r = adjoint_ratio(prec, steps=args.steps)
+    log(f"[bench] adjoint: {r}")
+    out = dict(metric=f"adjoint/forward cost ratio ({args.workload})",
+               value=round(r["backward_over_forward"], 4), unit="backward time / forward time",
+               n_gpus=1, steps=args.steps, warmup=0, ms_per_step=round(r["backward_ms_per_step"], 5),
+               higher_is_better=False, scaling="weak", vs_baseline=None,
+               dtype="f32" if prec == W.FP32 else "f64", data="synthetic",
+               config=dict(workload="adjoint96_Ra1e4_Pr1_Ste0.1_ckpt100", cells=96**3),
+               extras=r)
+    print(json.dumps(out), flush=True)
+
+
 def two_d_validations():
     """Sec. 3.2 at the paper's sizes on y-periodic slabs, FP32: solidification
     in a corner (400 x 400, to Fo = 0.25 with l_c = 400) and melting with
@@ -295,7 +341,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="cavity128_fp32",
                     choices=["cavity128_fp32", "cavity256_fp32", "cavity256_fp16s", "cavity256_bf16s",
-                             "cavity128_fp64", "batch64_fp32"],
+                             "cavity128_fp64", "batch64_fp32", "adjoint96_fp32", "adjoint96_fp64"],
                     help="cavity timed for the main line (profiling of the other kernels)")
     ap.add_argument("--launch", default=None,
                     help="block,grid,graph_steps,xcd_run instead of autotuning")
@@ -310,14 +356,26 @@ def main():
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     if args.calibrate_copy:
+        # a plain 1 GiB device copy, 10 times: the counter calibration, and
+        # the bandwidth a copy reaches on this GPU (read + write bytes / time)
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(10):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps(dict(calibrate_copy_bytes=a.numel() * 4, dispatches=10)))
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps(dict(calibrate_copy_bytes=a.numel() * 4, dispatches=11,
+                              copy_ms=round(ms, 4),
+                              copy_gbs_read_plus_write=round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1))))
         return
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.workload.startswith("adjoint96"):
+        adjoint_line(args)
+        return
 
     prec = {"fp32": W.FP32, "fp16s": W.FP16S, "bf16s": W.BF16S, "fp64": W.FP64}[
         args.workload.split("_")[1]]
@@ -372,6 +430,8 @@ def main():
             extras[f"table2_case{case}_fp32"] = r
             cv.close()
             del cv
+        extras["table2_case1_history_fp32"] = table2_history()
+        log(f"[bench] table 2 case 1 history: {extras['table2_case1_history_fp32']}")
         from paper_1703_02652_amd import Cavity
         bcfgs, _ = W.batch_cavities()
         bc = Cavity(bcfgs, device="cuda")
@@ -398,7 +458,7 @@ def main():
         log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
         extras["cavity128_full_run_fp32"] = full_run_128(main_r["launch"])
         log(f"[bench] 128^3 full run: {extras['cavity128_full_run_fp32']}")
-        extras["adjoint96_fp32_every_step"] = adjoint_ratio(W.FP32, every=1)
+        extras["adjoint96_fp32_every_step"] = adjoint_ratio(W.FP32, steps=200, every=1)
         log(f"[bench] adjoint fp32, a snapshot per step: {extras['adjoint96_fp32_every_step']}")
         extras.update(two_d_validations())
         log(f"[bench] 2D: {extras['corner400_fp32']} {extras['convection2d128_fp32']}")
