@@ -53,8 +53,10 @@ enum {
 };
 
 /* Population storage.  The shifted formats store f_a - w_a rho0 (the deviation
- * from rest); g_0, which carries the latent heat, is FP64 in the FP64 and FP32
- * formats and FP32 in the 16-bit ones; the enthalpy -> (T, f_l) update is
+ * from rest), and the 16-bit ones g_a - w_a C_p,ref T_shift for a = 1..6 (the
+ * deviation from rest at T_shift, a per-cavity reference temperature); g_0,
+ * which carries the latent heat, is FP64 in the FP64 and FP32 formats and
+ * FP32 in the 16-bit ones; the enthalpy -> (T, f_l) update is
  * FP64 and collision arithmetic FP32 for every format but FP64. */
 enum { LBPC_FP64 = 0, LBPC_FP32 = 1, LBPC_FP16S = 2, LBPC_BF16S = 3 };
 enum { LBPC_SRT = 0, LBPC_MRT = 1 };
@@ -86,6 +88,7 @@ typedef struct lbpc_config {
   double omega_T, cp_s, cp_l, cp_ref, lambda_s, lambda_l, latent, T_m, rho0;
   double nu, s_e, s_eps, s_q, s_pi, s_t, g_beta, T_ref;
   double sigma_override[7];
+  double T_shift;       /* 16-bit formats: g_1..6 stored as g_a - (omega_T / 2) cp_ref T_shift */
 } lbpc_config;
 
 typedef struct lbpc_ctx lbpc_ctx;

@@ -38,7 +38,7 @@ class LbpcConfig(ctypes.Structure):
         ("rho0", ctypes.c_double), ("nu", ctypes.c_double), ("s_e", ctypes.c_double),
         ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double), ("s_pi", ctypes.c_double),
         ("s_t", ctypes.c_double), ("g_beta", ctypes.c_double), ("T_ref", ctypes.c_double),
-        ("sigma_override", ctypes.c_double * 7),
+        ("sigma_override", ctypes.c_double * 7), ("T_shift", ctypes.c_double),
     ]
 
 

@@ -290,7 +290,8 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
     g[0] = static_cast<R>(g0d);
 #pragma unroll
     for (int a = 1; a < 7; ++a) g[a] = dec(buf_ld<S>(plane_rsrc(st.g + (a - 1) * pl, pb), oc));
-    const R s6 = moving_sum(g);
+    R s6 = moving_sum(g);
+    if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
     const double hd = g0d + static_cast<double>(s6);
     double Td, fld;
     phase_rule(c, hd, Td, fld);
@@ -385,7 +386,9 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         uxb += Q7X[a] * e_hq;
         uyb += Q7Y[a] * e_hq;
         uzb += Q7Z[a] * e_hq;
-        sigb += -(g[a] - geq) * lg[a];
+        R ga = g[a];
+        if constexpr (kShiftG<P>) ga += pars<R>(c).gshift;
+        sigb += -(ga - geq) * lg[a];
       }
       Tb += static_cast<R>(0.5 * c.omega_T * c.cp_ref) * wTb + static_cast<R>(0.5) * cp * hqb;
       cpb += static_cast<R>(0.5) * T * hqb;
@@ -450,7 +453,9 @@ k_adj_seed(const CavParams* __restrict__ cavp, const char* __restrict__ state,
   R g[7];
 #pragma unroll
   for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
-  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(moving_sum(g));
+  R s6 = moving_sum(g);
+  if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
+  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(s6);
   const double dfl = (h > c.hs && h < c.hl) ? c.inv_dh : 0.0;
   const R v = static_cast<R>(scale * dfl);
   R lf[19], lg[7];
@@ -480,7 +485,9 @@ k_adj_T0(const CavParams* __restrict__ cavp, const char* __restrict__ state0,
   R g[7];
 #pragma unroll
   for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
-  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(moving_sum(g));
+  R s6 = moving_sum(g);
+  if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
+  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(s6);
   const double dh0 = h <= c.hs ? c.cp_s : c.cp_l;
   double s = 0.0;
 #pragma unroll

@@ -17,6 +17,7 @@ template <class R> struct Pars {
   R lam_s, dlam, inv_rcw;       // lambda(f_l) = lam_s + f_l dlam
   R cp_s, dcp;                  // C_p(f_l) = cp_s + f_l dcp
   R w3, w21, whalf, wabb;       // 3, 21, 1/2 and 1 times omega_T C_p,ref
+  R gshift;                     // (omega_T / 2) C_p,ref T_shift (16-bit formats), else 0
   R sig_ovr[7];
 };
 
@@ -44,6 +45,7 @@ struct alignas(16) CavParams {
   // flow
   double s_nu, s_e, s_eps, s_q, s_pi, s_t, g_beta_rho0, T_ref;
   double fshift;                // rho0 for shifted storage, 0 for raw FP64
+  double gshift;                // stored g_1..6 = g_a - gshift (16-bit formats; 0 otherwise)
   Pars<float> pf;               // the constants above in FP32
   Pars<double> pd;              // and in FP64
 };

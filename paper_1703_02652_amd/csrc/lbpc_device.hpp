@@ -35,6 +35,14 @@ template <> struct Fmt<P32> { using S = float;    using S0 = double; using R = f
 template <> struct Fmt<P16> { using S = _Float16; using S0 = float;  using R = float; };
 template <> struct Fmt<PB16> { using S = __bf16;  using S0 = float;  using R = float; };
 
+// The 16-bit formats store the moving enthalpy populations as deviations from
+// a reference, g_a - (omega_T / 2) C_p,ref T_shift (a = 1..6), which spends
+// their few mantissa bits on what differs from it; the other formats store
+// g_a.  Kernels work on the stored values and add the reference where the
+// full populations enter (their sum h, the SRT equilibrium, the
+// anti-bounce-back rule).
+template <int P> constexpr bool kShiftG = P == P16 || P == PB16;
+
 __device__ __forceinline__ double dec(double v) { return v; }
 __device__ __forceinline__ float dec(float v) { return v; }
 __device__ __forceinline__ float dec(_Float16 v) { return static_cast<float>(v); }
@@ -418,10 +426,11 @@ __device__ __forceinline__ R enth_collide_mrt(const CavParams& c, R* g, R s6, R 
 
 // D3Q7 SRT (BGK) collision, Eq. (5)-(8): g^eq_0 = h - 3 omega_T C_p,ref T,
 // g^eq_a = (omega_T / 2) C_p,ref T + (u.e_a / 2) C_p T.
-template <class R>
+template <class R, bool SHIFT = false>
 __device__ __forceinline__ R enth_collide_srt(const CavParams& c, R* g, R s6, R T, R cp, R ux,
                                               R uy, R uz, R inv_tau) {
-  const R wT = pars<R>(c).whalf * T;
+  R wT = pars<R>(c).whalf * T;
+  if constexpr (SHIFT) wT -= pars<R>(c).gshift;  // g holds g_a - gshift
   const R hq = static_cast<R>(0.5) * cp * T;
   const R dg0 = -inv_tau * (pars<R>(c).w3 * T - s6);
   g[1] -= inv_tau * (g[1] - (wT + hq * ux));
@@ -535,7 +544,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
       } else {
         // enthalpy -> (T, f_l) in FP64 (the moving populations are small; their
         // sum is formed in the compute type)
-        const R s6 = moving_sum(g);
+        R s6 = moving_sum(g);
+        if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
         const double hd = g0d + static_cast<double>(s6);
         double Td, fld;
         phase_rule(c, hd, Td, fld);
@@ -555,7 +565,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
         }
         const R sig = sigma_chi<R>(c, fl);
         const R dg0 = MRT ? enth_collide_mrt<R>(c, g, s6, T, cp, ux, uy, uz, sig)
-                          : enth_collide_srt<R>(c, g, s6, T, cp, ux, uy, uz, sig);
+                          : enth_collide_srt<R, kShiftG<P>>(c, g, s6, T, cp, ux, uy, uz, sig);
 
         // stream: push every post-collision population along its link.  With
         // walls on all six faces a link either stays inside the cavity (target
@@ -613,7 +623,8 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
             if (c.bc[face] == BC_DIRICHLET) {
               // anti-bounce-back: g_abar(x) = -g*_a(x) + 2 w C_p,ref T_w
               const double Tw = c.tw[c.twface[face] + face_node(c, s, face)];
-              const R back = -g[a] + pars<R>(c).wabb * static_cast<R>(Tw);
+              R back = -g[a] + pars<R>(c).wabb * static_cast<R>(Tw);
+              if constexpr (kShiftG<P>) back -= static_cast<R>(2) * pars<R>(c).gshift;
               buf_st<S>(rs_back, oc, enc<S>(back));
               flux += static_cast<double>(back) - static_cast<double>(g[a]);
             } else {
@@ -656,7 +667,8 @@ k_init(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
     const double T = T0 ? T0[c.cell_off + cell] : c.T_m;
     const double h0 = T <= c.T_m ? c.cp_s * T : c.cp_l * T + c.latent;
     out.g0[cell] = static_cast<S0>(h0 - 3.0 * c.omega_T * c.cp_ref * T);
-    const double ga = 0.5 * c.omega_T * c.cp_ref * T;
+    double ga = 0.5 * c.omega_T * c.cp_ref * T;
+    if constexpr (kShiftG<P>) ga -= c.gshift;
 #pragma unroll
     for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(ga);
   }
@@ -688,7 +700,8 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
       g[0] = static_cast<R>(g0d);
 #pragma unroll
       for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
-      const R s6 = moving_sum(g);
+      R s6 = moving_sum(g);
+      if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
       const double h = g0d + static_cast<double>(s6);
       double T, fl;
       phase_rule(c, h, T, fl);
@@ -708,9 +721,11 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
         const R sig = sigma_chi<R>(c, flr);
         const R ux = FLOW ? q.ux : R(0), uy = FLOW ? q.uy : R(0), uz = FLOW ? q.uz : R(0);
         if (MRT) enth_collide_mrt<R>(c, g, s6, Tr, cp, ux, uy, uz, sig);
-        else enth_collide_srt<R>(c, g, s6, Tr, cp, ux, uy, uz, sig);
+        else enth_collide_srt<R, kShiftG<P>>(c, g, s6, Tr, cp, ux, uy, uz, sig);
         const double Tw = c.tw[c.twface[0] + face_node(c, st, 0)];
-        acc[3] = c.omega_T * c.cp_ref * Tw - 2.0 * static_cast<double>(g[2]);
+        double g2 = static_cast<double>(g[2]);
+        if constexpr (kShiftG<P>) g2 += c.gshift;
+        acc[3] = c.omega_T * c.cp_ref * Tw - 2.0 * g2;
       }
       acc[0] = h;
       acc[1] = rho;
@@ -735,7 +750,9 @@ k_fields(const CavParams* __restrict__ cavp, const char* __restrict__ src, uint3
   R g[7];
 #pragma unroll
   for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
-  const double h = static_cast<double>(in.g0[cell]) + static_cast<double>(moving_sum(g));
+  R s6 = moving_sum(g);
+  if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
+  const double h = static_cast<double>(in.g0[cell]) + static_cast<double>(s6);
   double T, fl;
   phase_rule(c, h, T, fl);
   double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
@@ -778,7 +795,11 @@ k_get_state(const CavParams* __restrict__ cavp, const char* __restrict__ src,
   }
   g[cell] = static_cast<double>(in.g0[cell]);
 #pragma unroll
-  for (int a = 1; a < 7; ++a) g[a * n + cell] = static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+  for (int a = 1; a < 7; ++a) {
+    double v = static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
+    if constexpr (kShiftG<P>) v += c.gshift;
+    g[a * n + cell] = v;
+  }
 }
 
 template <int P, bool FLOW>
@@ -798,7 +819,11 @@ k_set_state(const CavParams* __restrict__ cavp, char* __restrict__ dst,
   }
   out.g0[cell] = static_cast<S0>(g[cell]);
 #pragma unroll
-  for (int a = 1; a < 7; ++a) out.g[(a - 1) * pl + cell] = enc<S>(g[a * n + cell]);
+  for (int a = 1; a < 7; ++a) {
+    double v = g[a * n + cell];
+    if constexpr (kShiftG<P>) v -= c.gshift;
+    out.g[(a - 1) * pl + cell] = enc<S>(v);
+  }
 }
 
 }  // namespace lbpc

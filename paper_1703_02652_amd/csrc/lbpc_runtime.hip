@@ -234,8 +234,9 @@ bool validate(const lbpc_config* cfgs, int batch, std::string& err) {
     if (!(c.cp_s > 0 && c.cp_l > 0 && c.cp_ref > 0)) return bad("specific heats must be > 0");
     if (!(c.lambda_s > 0 && c.lambda_l > 0)) return bad("conductivities must be > 0");
     if (!(c.rho0 > 0)) return bad("rho0 must be > 0");
-    if (!std::isfinite(c.T_m) || !std::isfinite(c.T_ref) || !std::isfinite(c.g_beta))
-      return bad("T_m, T_ref and g_beta must be finite");
+    if (!std::isfinite(c.T_m) || !std::isfinite(c.T_ref) || !std::isfinite(c.g_beta) ||
+        !std::isfinite(c.T_shift))
+      return bad("T_m, T_ref, T_shift and g_beta must be finite");
     if (!(c.cp_l * c.T_m + c.latent > c.cp_s * c.T_m)) return bad("h_l must exceed h_s");
     if (c.flow) {
       if (!(c.nu > 0)) return bad("nu must be > 0");
@@ -344,6 +345,7 @@ template <class R> void fill_pars(const CavParams& p, Pars<R>& q) {
   q.w21 = static_cast<R>(21.0 * p.omega_T * p.cp_ref);
   q.whalf = static_cast<R>(0.5 * p.omega_T * p.cp_ref);
   q.wabb = static_cast<R>(p.omega_T * p.cp_ref);
+  q.gshift = static_cast<R>(p.gshift);
   for (int k = 0; k < 7; ++k) q.sig_ovr[k] = static_cast<R>(p.sig_ovr[k]);
 }
 
@@ -396,6 +398,7 @@ CavParams make_params(const lbpc_config& c, const Layout& L, int i, const double
   p.g_beta_rho0 = c.g_beta * c.rho0;
   p.T_ref = c.T_ref;
   p.fshift = c.precision == LBPC_FP64 ? 0.0 : c.rho0;
+  p.gshift = c.precision >= LBPC_FP16S ? 0.5 * c.omega_T * c.cp_ref * c.T_shift : 0.0;
   fill_pars(p, p.pf);
   fill_pars(p, p.pd);
   return p;

@@ -71,7 +71,7 @@ def test_config_struct_layout_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b([a-zA-Z_][a-zA-Z_0-9]*)\s*(?:\[\d+\])?\s*[,;]", body)
     assert names == [n for n, _ in LbpcConfig._fields_]
-    assert ctypes.sizeof(LbpcConfig) == 6 * 4 + 6 * 4 + 6 * 8 + 17 * 8 + 7 * 8
+    assert ctypes.sizeof(LbpcConfig) == 6 * 4 + 6 * 4 + 6 * 8 + 17 * 8 + 7 * 8 + 8
 
 
 def test_bench_refuses_more_than_one_gpu():

@@ -45,7 +45,7 @@ def test_degenerate_lattices_match_oracle(case, flow):
         assert rel(fg, st[0]) < 1e-12
 
 
-@pytest.mark.parametrize("prec", [W.FP32, W.FP16S])
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16S, W.BF16S])
 def test_cavity256_full_size_one_step_against_oracle(prec):
     """Full-size 256^3 precision cavity (Ra 1e6, Pr 0.02) in the launch shape the
     benchmark tunes: after 100 steps the oracle's FP64 step from the GPU state
@@ -62,13 +62,14 @@ def test_cavity256_full_size_one_step_against_oracle(prec):
     ref = oracle.run(dict(cfg, precision=W.FP64), st, 1)
     dev = np.abs(ref[0] - W19.reshape(19, 1, 1, 1) * cfg["rho0"]).max()
     ef, eg = absdiff(f1, ref[0]), absdiff(g1, ref[1])
-    print(f"256^3 {['fp64', 'fp32', 'fp16s'][prec]} one step (launch {cav.get_launch()}): "
+    print(f"256^3 {['fp64', 'fp32', 'fp16s', 'bf16s'][prec]} one step (launch {cav.get_launch()}): "
           f"max|df| {ef:.2e} (max deviation {dev:.2e}), max|dg| {eg:.2e}")
-    # shifted storage rounds the deviation f - w rho0 (FP32: 24 bits, FP16: 11)
-    # and g_1..6; deviations near 2e-5 are FP16 subnormals (spacing 2^-24, below
-    # the smallest normal 6.1e-5): observed FP32 6.7e-12, FP16 3.0e-8 = 2^-25
-    bits = 20 if prec == W.FP32 else 10
-    floor = 1e-13 if prec == W.FP32 else 2.0 ** -25
+    # shifted storage rounds the deviation f - w rho0 (FP32: 24 bits, FP16: 11,
+    # BF16: 8) and g_1..6; deviations near 2e-5 are FP16 subnormals (spacing
+    # 2^-24, below the smallest normal 6.1e-5): observed FP32 6.7e-12, FP16
+    # 3.0e-8 = 2^-25
+    bits = {W.FP32: 20, W.FP16S: 10, W.BF16S: 7}[prec]
+    floor = {W.FP32: 1e-13, W.FP16S: 2.0 ** -25, W.BF16S: 0.0}[prec]
     assert ef < 2.0 ** -bits * dev + floor
     assert eg < 2.0 ** -bits * np.abs(ref[1][1:]).max()
     assert abs(cav.budgets()[0, 1] / 256**3 - 1.0) < 1e-5
