@@ -28,9 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # once in the storage type (FP64 416, FP32 208, 16-bit populations with an FP32
 # g_0 108).  The roofline fraction uses these.
 BYTES_PER_CELL = {0: 416, 1: 208, 2: 108, 3: 108}
-# Bytes the storage format actually moves: the FP32 format keeps g_0 in FP64
-# (25 x 4 + 8 = 108 B per copy), the others match the algorithmic count.
-FORMAT_BYTES_PER_CELL = {0: 416, 1: 216, 2: 108, 3: 108}
+# Bytes the storage format actually moves: the FP32 format keeps g_0 as an FP32
+# value and a 16-bit correction (25 x 4 + 6 = 106 B per copy), the others
+# match the algorithmic count.
+FORMAT_BYTES_PER_CELL = {0: 416, 1: 212, 2: 108, 3: 108}
 
 
 def measured_traffic():

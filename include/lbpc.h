@@ -55,9 +55,10 @@ enum {
 /* Population storage.  The shifted formats store f_a - w_a rho0 (the deviation
  * from rest), and the 16-bit ones g_a - w_a C_p,ref T_shift for a = 1..6 (the
  * deviation from rest at T_shift, a per-cavity reference temperature); g_0,
- * which carries the latent heat, is FP64 in the FP64 and FP32 formats and
- * FP32 in the 16-bit ones; the enthalpy -> (T, f_l) update is
- * FP64 and collision arithmetic FP32 for every format but FP64. */
+ * which carries the latent heat, is FP64 in the FP64 format, an FP32 value
+ * plus a 16-bit correction (40 significant bits, 6 bytes) in the FP32 format
+ * and FP32 in the 16-bit ones; the enthalpy -> (T, f_l) update is FP64 and
+ * collision arithmetic FP32 for every format but FP64. */
 enum { LBPC_FP64 = 0, LBPC_FP32 = 1, LBPC_FP16S = 2, LBPC_BF16S = 3 };
 enum { LBPC_SRT = 0, LBPC_MRT = 1 };
 

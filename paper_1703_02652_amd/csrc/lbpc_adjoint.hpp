@@ -286,7 +286,13 @@ k_adjoint(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
 #pragma unroll
       for (int a = 0; a < 19; ++a) d[a] = dec(buf_ld<S>(plane_rsrc(st.f + a * pl, pb), oc));
     }
-    const double g0d = buf_ld<S0>(plane_rsrc(st.g0, pb0), oc0);
+    double g0d;
+    if constexpr (kSplitG0<P>)
+      g0d = g0_join(buf_ld<S0>(plane_rsrc(st.g0, pb0), oc0),
+                    buf_ld<int16_t>(plane_rsrc(st.g0lo, static_cast<uint32_t>(pl) * 2u),
+                                    static_cast<uint32_t>(cell) * 2u));
+    else
+      g0d = buf_ld<S0>(plane_rsrc(st.g0, pb0), oc0);
     g[0] = static_cast<R>(g0d);
 #pragma unroll
     for (int a = 1; a < 7; ++a) g[a] = dec(buf_ld<S>(plane_rsrc(st.g + (a - 1) * pl, pb), oc));
@@ -455,7 +461,7 @@ k_adj_seed(const CavParams* __restrict__ cavp, const char* __restrict__ state,
   for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
   R s6 = moving_sum(g);
   if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
-  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(s6);
+  const double h = load_g0<P>(st, cell) + static_cast<double>(s6);
   const double dfl = (h > c.hs && h < c.hl) ? c.inv_dh : 0.0;
   const R v = static_cast<R>(scale * dfl);
   R lf[19], lg[7];
@@ -487,7 +493,7 @@ k_adj_T0(const CavParams* __restrict__ cavp, const char* __restrict__ state0,
   for (int a = 1; a < 7; ++a) g[a] = dec(st.g[(a - 1) * pl + cell]);
   R s6 = moving_sum(g);
   if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
-  const double h = static_cast<double>(st.g0[cell]) + static_cast<double>(s6);
+  const double h = load_g0<P>(st, cell) + static_cast<double>(s6);
   const double dh0 = h <= c.hs ? c.cp_s : c.cp_l;
   double s = 0.0;
 #pragma unroll

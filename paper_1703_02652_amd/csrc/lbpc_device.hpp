@@ -26,14 +26,38 @@ namespace lbpc {
 // ---------------------------------------------------------------------------
 template <int P> struct Fmt;
 // g_0 carries the latent heat (h = g_0 + sum of the small moving populations):
-// FP64 storage keeps the small per-step enthalpy changes of a mushy cell from
-// being rounded away against its large value over long FP32 runs.  The 16-bit
-// formats store it in FP32: their own rounding of the moving populations is
-// far larger than what FP32 g_0 loses, and it saves 8 of 116 bytes per cell.
+// FP32 alone would round the small per-step enthalpy changes of a mushy cell
+// away against its large value over long runs.  The FP32 format therefore
+// stores g_0 as an FP32 value and a 16-bit correction (kSplitG0, 6 bytes, 40
+// significant bits; see g0_join), FP64 stores it as it is, and the 16-bit
+// formats in FP32: their own rounding of the moving populations is far larger
+// than what FP32 g_0 loses.
 template <> struct Fmt<P64> { using S = double;   using S0 = double; using R = double; };
-template <> struct Fmt<P32> { using S = float;    using S0 = double; using R = float; };
+template <> struct Fmt<P32> { using S = float;    using S0 = float;  using R = float; };
 template <> struct Fmt<P16> { using S = _Float16; using S0 = float;  using R = float; };
 template <> struct Fmt<PB16> { using S = __bf16;  using S0 = float;  using R = float; };
+template <int P> constexpr bool kSplitG0 = P == P32;
+
+// g_0 of the FP32 format: hi = g_0 rounded to FP32, lo = the rest in units of
+// ulp(hi) / 2^16, rounded to an int16 (|rest| <= ulp(hi) / 2, so |lo| <=
+// 2^15).  g_0 = hi + lo * ulp(hi) / 2^16 to within ulp(hi) / 2^17, i.e. 40
+// significant bits.  Zero and FP32 subnormals use the subnormal ulp.
+__device__ __forceinline__ int g0_lo_exp(float hi) {
+  const uint32_t e = (__float_as_uint(hi) >> 23) & 0xffu;
+  return static_cast<int>(e == 0u ? 1u : e) - 127 - 23 - 16;
+}
+__device__ __forceinline__ double pow2(int k) {  // 2^k for -1022 <= k <= 1023
+  return __longlong_as_double(static_cast<long long>(k + 1023) << 52);
+}
+__device__ __forceinline__ double g0_join(float hi, int16_t lo) {
+  return static_cast<double>(hi) + static_cast<double>(lo) * pow2(g0_lo_exp(hi));
+}
+__device__ __forceinline__ void g0_split(double v, float& hi, int16_t& lo) {
+  hi = static_cast<float>(v);
+  // v - hi is exact in FP64; scaling by a power of two is exact
+  const double q = rint((v - static_cast<double>(hi)) * pow2(-g0_lo_exp(hi)));
+  lo = static_cast<int16_t>(fmin(fmax(q, -32768.0), 32767.0));
+}
 
 // The 16-bit formats store the moving enthalpy populations as deviations from
 // a reference, g_a - (omega_T / 2) C_p,ref T_shift (a = 1..6), which spends
@@ -100,6 +124,13 @@ template <> __device__ __forceinline__ __bf16 buf_ld<__bf16>(__amdgpu_buffer_rsr
   return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(
                                         r, static_cast<int>(off), 0, kNonTemporal));
 }
+template <> __device__ __forceinline__ int16_t buf_ld<int16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(int16_t, __builtin_amdgcn_raw_buffer_load_b16(
+                                         r, static_cast<int>(off), 0, kNonTemporal));
+}
+template <> __device__ __forceinline__ void buf_st<int16_t>(__amdgpu_buffer_rsrc_t r, uint32_t off, int16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, static_cast<int>(off), 0, 0);
+}
 template <> __device__ __forceinline__ void buf_st<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
   using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, static_cast<int>(off), 0, 0);
@@ -119,7 +150,8 @@ template <int P> struct View {
   using S0 = typename Fmt<P>::S0;
   S* f;     // 19 planes (only with flow)
   S* g;     // g_1..g_6 planes
-  S0* g0;   // g_0 plane
+  S0* g0;   // g_0 plane (the FP32 part in the FP32 format)
+  int16_t* g0lo;  // FP32 format: the correction plane of g_0 (kSplitG0)
   int64_t plane;
 };
 
@@ -132,7 +164,26 @@ __device__ __forceinline__ View<P> view(const char* region, const CavParams& c, 
   v.f = reinterpret_cast<S*>(const_cast<char*>(region) + c.off);
   v.g = v.f + (flow ? 19 * c.plane : 0);
   v.g0 = reinterpret_cast<S0*>(v.g + 6 * c.plane);
+  v.g0lo = reinterpret_cast<int16_t*>(v.g0 + c.plane);
   return v;
+}
+
+// g_0 of one cell as FP64, and its store, for the kernels that address the
+// planes through plain pointers.
+template <int P> __device__ __forceinline__ double load_g0(const View<P>& v, int32_t cell) {
+  if constexpr (kSplitG0<P>) return g0_join(v.g0[cell], v.g0lo[cell]);
+  else return static_cast<double>(v.g0[cell]);
+}
+template <int P> __device__ __forceinline__ void store_g0(const View<P>& v, int32_t cell, double x) {
+  if constexpr (kSplitG0<P>) {
+    float hi;
+    int16_t lo;
+    g0_split(x, hi, lo);
+    v.g0[cell] = hi;
+    v.g0lo[cell] = lo;
+  } else {
+    v.g0[cell] = static_cast<typename Fmt<P>::S0>(x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -491,6 +542,22 @@ __device__ __forceinline__ int reversed_slot(int t, int ntiles) {
   return (per_xcd - 1 - j) * kXcds + k;
 }
 
+// g_0 store through buffer resources (step kernel).
+template <int P>
+__device__ __forceinline__ void store_g0_buf(const View<P>& out, uint32_t pb0, uint32_t oc0,
+                                             uint32_t pbl, uint32_t ocl, double x) {
+  using S0 = typename Fmt<P>::S0;
+  if constexpr (kSplitG0<P>) {
+    float hi;
+    int16_t lo;
+    g0_split(x, hi, lo);
+    buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, hi);
+    buf_st<int16_t>(plane_rsrc(out.g0lo, pbl), ocl, lo);
+  } else {
+    buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, static_cast<S0>(x));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The fused step
 // ---------------------------------------------------------------------------
@@ -521,13 +588,19 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
       const uint32_t pb0 = static_cast<uint32_t>(pl) * static_cast<uint32_t>(sizeof(S0));
       const uint32_t oc = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S));
       const uint32_t oc0 = static_cast<uint32_t>(cell) * static_cast<uint32_t>(sizeof(S0));
+      const uint32_t pbl = static_cast<uint32_t>(pl) * 2u, ocl = static_cast<uint32_t>(cell) * 2u;
       R d[19];
       R g[7];
       if (FLOW) {
 #pragma unroll
         for (int a = 0; a < 19; ++a) d[a] = dec(buf_ld<S>(plane_rsrc(in.f + a * pl, pb), oc));
       }
-      const double g0d = buf_ld<S0>(plane_rsrc(in.g0, pb0), oc0);
+      double g0d;
+      if constexpr (kSplitG0<P>)
+        g0d = g0_join(buf_ld<S0>(plane_rsrc(in.g0, pb0), oc0),
+                      buf_ld<int16_t>(plane_rsrc(in.g0lo, pbl), ocl));
+      else
+        g0d = buf_ld<S0>(plane_rsrc(in.g0, pb0), oc0);
       g[0] = static_cast<R>(g0d);
 #pragma unroll
       for (int a = 1; a < 7; ++a) g[a] = dec(buf_ld<S>(plane_rsrc(in.g + (a - 1) * pl, pb), oc));
@@ -537,7 +610,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
 #pragma unroll
           for (int a = 0; a < 19; ++a) buf_st<S>(plane_rsrc(out.f + a * pl, pb), oc, enc<S>(d[a]));
         }
-        buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, static_cast<S0>(g0d));
+        store_g0_buf<P>(out, pb0, oc0, pbl, ocl, g0d);
 #pragma unroll
         for (int a = 1; a < 7; ++a)
           buf_st<S>(plane_rsrc(out.g + (a - 1) * pl, pb), oc, enc<S>(g[a]));
@@ -598,7 +671,7 @@ k_step(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
             }
           }
         }
-        buf_st<S0>(plane_rsrc(out.g0, pb0), oc0, static_cast<S0>(g0d + static_cast<double>(dg0)));
+        store_g0_buf<P>(out, pb0, oc0, pbl, ocl, g0d + static_cast<double>(dg0));
         double flux = 0.0;
 #pragma unroll
         for (int a = 1; a < 7; ++a) {
@@ -666,7 +739,7 @@ k_init(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, int n
     }
     const double T = T0 ? T0[c.cell_off + cell] : c.T_m;
     const double h0 = T <= c.T_m ? c.cp_s * T : c.cp_l * T + c.latent;
-    out.g0[cell] = static_cast<S0>(h0 - 3.0 * c.omega_T * c.cp_ref * T);
+    store_g0<P>(out, cell, h0 - 3.0 * c.omega_T * c.cp_ref * T);
     double ga = 0.5 * c.omega_T * c.cp_ref * T;
     if constexpr (kShiftG<P>) ga -= c.gshift;
 #pragma unroll
@@ -696,7 +769,7 @@ k_measure(const CavParams* __restrict__ cavs, const int2* __restrict__ tiles, in
 #pragma unroll
         for (int a = 0; a < 19; ++a) d[a] = dec(in.f[a * pl + cell]);
       }
-      const double g0d = in.g0[cell];
+      const double g0d = load_g0<P>(in, cell);
       g[0] = static_cast<R>(g0d);
 #pragma unroll
       for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
@@ -752,7 +825,7 @@ k_fields(const CavParams* __restrict__ cavp, const char* __restrict__ src, uint3
   for (int a = 1; a < 7; ++a) g[a] = dec(in.g[(a - 1) * pl + cell]);
   R s6 = moving_sum(g);
   if constexpr (kShiftG<P>) s6 += static_cast<R>(6) * pars<R>(c).gshift;
-  const double h = static_cast<double>(in.g0[cell]) + static_cast<double>(s6);
+  const double h = load_g0<P>(in, cell) + static_cast<double>(s6);
   double T, fl;
   phase_rule(c, h, T, fl);
   double rho = 0.0, u[3] = {0.0, 0.0, 0.0};
@@ -793,7 +866,7 @@ k_get_state(const CavParams* __restrict__ cavp, const char* __restrict__ src,
     for (int a = 0; a < 19; ++a)
       f[a * n + cell] = static_cast<double>(dec(in.f[a * pl + cell])) + W19[a] * c.fshift;
   }
-  g[cell] = static_cast<double>(in.g0[cell]);
+  g[cell] = load_g0<P>(in, cell);
 #pragma unroll
   for (int a = 1; a < 7; ++a) {
     double v = static_cast<double>(dec(in.g[(a - 1) * pl + cell]));
@@ -817,7 +890,7 @@ k_set_state(const CavParams* __restrict__ cavp, char* __restrict__ dst,
 #pragma unroll
     for (int a = 0; a < 19; ++a) out.f[a * pl + cell] = enc<S>(f[a * n + cell] - W19[a] * c.fshift);
   }
-  out.g0[cell] = static_cast<S0>(g[cell]);
+  store_g0<P>(out, cell, g[cell]);
 #pragma unroll
   for (int a = 1; a < 7; ++a) {
     double v = g[a * n + cell];

@@ -189,7 +189,8 @@ struct Layout {
 };
 
 size_t pop_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
-size_t g0_bytes(int prec) { return prec <= 1 ? 8 : 4; }  // g_0: FP64, or FP32 in the 16-bit formats
+// g_0: FP64; FP32 + an int16 correction in the FP32 format; FP32 in the 16-bit formats
+size_t g0_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 6 : 4; }
 
 int64_t face_size(const lbpc_config& c, int face) {
   const int d = face / 2;
