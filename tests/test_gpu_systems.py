@@ -282,23 +282,28 @@ def test_cavity128_full_size_one_step_against_oracle():
 
 @pytest.mark.parametrize("Pr", [0.02, 6.2])
 def test_sixteen_bit_errors_at_64_against_fp64_oracle(Pr):
-    """Precision workload shape (Ra 1e6) at 64^3, 300 steps: FP32, FP16 and BF16
-    storage against the FP64 oracle; errors are reported (printed) and bounded
-    loosely; FP32 keeps the liquid fraction within 1e-5."""
+    """Precision workload shape (Ra 1e6) at 64^3, 2000 steps: FP32, FP16 and
+    BF16 storage against the FP64 oracle.  Errors of T, f_l and |u| are
+    reported (printed: max and RMS) and bounded loosely for the 16-bit
+    formats; FP32 keeps every cell's liquid fraction within 1e-5."""
+    steps = 2000
     cfg64 = W.precision_cavity(64, Pr, precision=W.FP64)
-    ref = oracle.run(cfg64, oracle.init_state(cfg64), 300)
+    ref = oracle.run(cfg64, oracle.init_state(cfg64), steps)
     rf = oracle.fields(cfg64, ref)
     umag_ref = np.sqrt(rf["ux"] ** 2 + rf["uy"] ** 2 + rf["uz"] ** 2)
-    for prec, lim in ((W.FP32, 1e-5), (W.FP16S, 5e-3), (W.BF16S, 5e-2)):
+    for prec, lim in ((W.FP32, 1e-5), (W.FP16S, 1e-2), (W.BF16S, 1e-1)):
         cav = make_cavity(dict(cfg64, precision=prec))
-        cav.step(300)
+        cav.step(steps)
         fl = cav.fields(names=("T", "fl", "u"))
         umag = np.sqrt(sum(fl[k].cpu().numpy() ** 2 for k in ("ux", "uy", "uz")))
-        eT, efl = absdiff(fl["T"], rf["T"]), absdiff(fl["fl"], rf["fl"])
-        eu = np.abs(umag - umag_ref).max()
-        print(f"Pr {Pr} prec {prec}: max|dT| {eT:.2e} max|dfl| {efl:.2e} max|d|u|| {eu:.2e} "
-              f"(max|u| {umag_ref.max():.2e})")
-        assert efl < lim and eT < 10 * lim
+        dT = np.abs(fl["T"].cpu().numpy() - rf["T"])
+        dfl = np.abs(fl["fl"].cpu().numpy() - rf["fl"])
+        du = np.abs(umag - umag_ref)
+        print(f"Pr {Pr} prec {prec} {steps} steps: |dT| max {dT.max():.2e} rms "
+              f"{np.sqrt((dT ** 2).mean()):.2e}; |dfl| max {dfl.max():.2e} rms "
+              f"{np.sqrt((dfl ** 2).mean()):.2e}; |d|u|| max {du.max():.2e} "
+              f"(max|u| {umag_ref.max():.2e}); d mean fl {abs(dfl.mean()):.2e}")
+        assert dfl.max() < lim and dT.max() < lim
         cav.close()
 
 
