@@ -3,10 +3,12 @@
 // translation units only.
 //
 // Layout: every cavity owns, inside a state region, 19 f planes, 6 planes for
-// g_1..g_6 and one plane for g_0, each plane `plane` elements long, cell index
+// g_1..g_6 and one plane for g_0 (followed by its int16 correction plane in
+// the FP32 format), each plane `plane` elements long, cell index
 // x + nx (y + ny z).  FP64 stores the populations as they are; the other
-// formats store f_a - w_a rho0 (deviation from rest); g_0 is FP64, or FP32 in
-// the 16-bit formats.
+// formats store f_a - w_a rho0 (deviation from rest), the 16-bit ones also
+// g_a relative to a reference (kShiftG); g_0 is FP64, FP32 + correction
+// (kSplitG0) or FP32 in the 16-bit formats.
 //
 // Step scheme: one thread per cell reads its own pre-collision populations
 // (aligned, coalesced), does both collisions in registers and pushes every
