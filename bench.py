@@ -401,9 +401,9 @@ def main():
                     bytes_per_cell=BYTES_PER_CELL[prec], bytes_per_launch=alg_bytes,
                     format_bytes_per_cell=FORMAT_BYTES_PER_CELL[prec],
                     kernel_ms=round(main_r["kernel_ms"], 5),
-                    time_source="mean duration of the step kernel: start and stop events of "
-                                "each launch (hipExtLaunchKernel) on the library's stream, over "
-                                "runs of back-to-back launches",
+                    time_source="mean time per step kernel over a captured graph of 14 "
+                                "back-to-back wall-inflow-partials steps, HIP events around "
+                                "each replay on the library's stream",
                     frac_of_step=round(step_gbs / HBM_PEAK_GBS, 4))
     cav.close()
     del cav

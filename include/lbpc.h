@@ -217,12 +217,12 @@ int lbpc_get_launch(const lbpc_ctx* ctx, int32_t* block, int32_t* grid_blocks,
  * milliseconds.  Synchronises the stream. */
 int lbpc_autotune(lbpc_ctx* ctx, int32_t trial_steps, double* host_ms_out);
 
-/* Advance nsteps with eager step-kernel launches on the library's stream:
- * runs of up to 15 back-to-back wall-inflow-partials steps (the kernel the
- * graphs run), each launched with a start and a stop event that the runtime
- * records at the start and the end of the kernel itself (hipExtLaunchKernel),
- * then one step with all partials, not counted.  The mean kernel duration in
- * milliseconds goes to host_ms_out.  Synchronises. */
+/* Time the step kernel as the graphs of lbpc_step run it: a captured graph of
+ * 14 back-to-back wall-inflow-partials steps, replayed ceil(nsteps / 14)
+ * times between one HIP event pair each on the library's stream; every replay
+ * is followed by two untimed eager steps (the second with all partials, which
+ * closes the budget ring), so the run advances 16 steps per replay.  The mean
+ * time per timed step in milliseconds goes to host_ms_out.  Synchronises. */
 int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
 
 /* Discrete adjoint of the loss L = sum over cells of f_l at the final step

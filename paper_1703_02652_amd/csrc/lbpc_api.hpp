@@ -90,9 +90,6 @@ struct StepArgs {
   int reverse;                  // 1: walk each XCD's queue positions from their end
   int flow, mrt;
   hipStream_t stream;
-  // non-null: timing events recorded at the start and the end of the kernel
-  // itself (hipExtLaunchKernel), for the kernel-duration timer
-  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
 
 struct AdjArgs {

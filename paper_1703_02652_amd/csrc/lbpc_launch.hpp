@@ -1,8 +1,6 @@
 // Host-side launchers of the per-format kernels.  Each kernel translation unit
 // includes this file once and instantiates the launchers for one format.
 #pragma once
-#include <hip/hip_ext.h>
-
 #include "lbpc_adjoint.hpp"
 #include "lbpc_device.hpp"
 
@@ -24,16 +22,9 @@ hipError_t launch_step(const StepArgs& a) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 grid(step_grid(a.ntiles, a.grid));
   const dim3 block(a.block);
-#define LBPC_STEP(FL, MR, BU)                                                                  \
-  do {                                                                                         \
-    if (a.ev_start)                                                                            \
-      hipExtLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.ev_start,     \
-                            a.ev_stop, 0, a.cavs, a.tiles, a.ntiles, a.reverse, a.src, a.dst,  \
-                            a.partials, a.sums, a.status);                                     \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
-                         a.ntiles, a.reverse, a.src, a.dst, a.partials, a.sums, a.status);     \
-  } while (0)
+#define LBPC_STEP(FL, MR, BU)                                                              \
+  hipLaunchKernelGGL((k_step<P, FL, MR, BU>), grid, block, 0, a.stream, a.cavs, a.tiles,  \
+                     a.ntiles, a.reverse, a.src, a.dst, a.partials, a.sums, a.status)
 #define LBPC_STEP_B(FL, MR)                                    \
   do {                                                         \
     if (a.budget == 2) LBPC_STEP(FL, MR, 2);                   \

@@ -471,11 +471,8 @@ int fail(lbpc_ctx* x, int code, const std::string& msg) {
   } while (0)
 
 hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partials, int budget,
-                         hipStream_t st, hipEvent_t ev_start = nullptr,
-                         hipEvent_t ev_stop = nullptr) {
+                         hipStream_t st) {
   StepArgs a;
-  a.ev_start = ev_start;
-  a.ev_stop = ev_stop;
   a.sums = x->d_sums;
   a.cavs = x->d_params;
   a.tiles = x->d_tiles;
@@ -1132,47 +1129,57 @@ int lbpc_time_step_kernel(lbpc_ctx* x, int32_t nsteps, double* host_ms_out) {
   if (!x || nsteps < 1) return fail(x, LBPC_EINVAL, "bad argument");
   int rc = flush(x);
   if (rc) return rc;
-  // Runs of back-to-back wall-inflow-partials steps (the kernel the graphs
-  // run), each launched with a start and a stop event that the runtime records
-  // at the start and the end of the kernel itself; the step that closes a
-  // reduction carries all partials and is not counted.
-  struct Events {
-    hipEvent_t e[2 * kRing] = {};
-    ~Events() {
-      for (hipEvent_t v : e)
-        if (v) (void)hipEventDestroy(v);
+  // The step kernel as the run's graphs hold it: a captured graph of kTimed
+  // back-to-back wall-inflow-partials steps, timed between one event pair per
+  // replay.  Each replay is followed by two untimed eager steps, the second
+  // with all partials, which close the ring and bring the state back to the
+  // region the graph starts from.
+  constexpr int kTimed = kRing - 2;
+  struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~Graph() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
     }
-  } ev;
-  for (hipEvent_t& v : ev.e) HIPCHK(x, hipEventCreate(&v));
-  auto one_step = [&](int budget, hipEvent_t e0, hipEvent_t e1) -> hipError_t {
-    double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
-    const hipError_t e = dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget,
-                                       x->stream, e0, e1);
-    x->cur ^= 1;
-    x->steps += 1;
-    x->pending += 1;
-    return e;
-  };
-  double total = 0.0, single = 0.0;
-  int64_t counted = 0, left = nsteps;
-  while (left > 0) {
-    const int k = static_cast<int>(std::min<int64_t>(left - 1, kRing - 1));
-    for (int i = 0; i < k; ++i) HIPCHK(x, one_step(1, ev.e[2 * i], ev.e[2 * i + 1]));
-    HIPCHK(x, one_step(2, ev.e[2 * kRing - 2], ev.e[2 * kRing - 1]));
-    HIPCHK(x, hipStreamSynchronize(x->stream));
-    float ms = 0.f;
-    for (int i = 0; i < k; ++i) {
-      HIPCHK(x, hipEventElapsedTime(&ms, ev.e[2 * i], ev.e[2 * i + 1]));
-      total += ms;
+  } tg;
+  HIPCHK(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  int c = x->cur;
+  for (int i = 0; i < kTimed && e == hipSuccess; ++i, c ^= 1)
+    e = dispatch_step(x, x->region[c], x->region[c ^ 1],
+                      x->d_part + static_cast<int64_t>(i) * x->L.max_waves, 1, x->cap);
+  const hipError_t e2 = hipStreamEndCapture(x->cap, &tg.g);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(x, LBPC_EHIP, std::string("timing graph capture: ") +
+                                  hipGetErrorString(e != hipSuccess ? e : e2));
+  HIPCHK(x, hipGraphInstantiate(&tg.e, tg.g, nullptr, nullptr, 0));
+  EventPair ev;
+  HIPCHK(x, ev.create());
+  const int runs = (nsteps + kTimed - 1) / kTimed;
+  double total = 0.0;
+  for (int r = 0; r < runs; ++r) {
+    HIPCHK(x, hipEventRecord(ev.e0, x->stream));
+    HIPCHK(x, hipGraphLaunch(tg.e, x->stream));
+    HIPCHK(x, hipEventRecord(ev.e1, x->stream));
+    x->steps += kTimed;
+    x->pending = kTimed;
+    for (int budget = 1; budget <= 2; ++budget) {
+      double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
+      HIPCHK(x, dispatch_step(x, x->region[x->cur], x->region[x->cur ^ 1], part, budget,
+                              x->stream));
+      x->cur ^= 1;
+      x->steps += 1;
+      x->pending += 1;
     }
-    counted += k;
-    HIPCHK(x, hipEventElapsedTime(&ms, ev.e[2 * kRing - 2], ev.e[2 * kRing - 1]));
-    single = ms;
-    left -= k + 1;
     rc = flush(x);
     if (rc) return rc;
+    HIPCHK(x, hipEventSynchronize(ev.e1));
+    float ms = 0.f;
+    HIPCHK(x, hipEventElapsedTime(&ms, ev.e0, ev.e1));
+    total += ms;
   }
-  if (host_ms_out) *host_ms_out = counted ? total / static_cast<double>(counted) : single;
+  if (host_ms_out) *host_ms_out = total / (static_cast<double>(runs) * kTimed);
   return LBPC_OK;
 }
 
