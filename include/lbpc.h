@@ -124,8 +124,8 @@ int lbpc_set_wall_T(lbpc_ctx* ctx, int32_t cavity, int32_t face, const double* d
  * and (49)-(54)) take the macroscopic fields of the same pre-collision state
  * (h, T, f_l by Eq. (2); rho, u by Eq. (55)-(56)), then both distributions
  * stream with the wall rules above.  Steps run in captured HIP graphs of up
- * to graph_steps steps (lbpc_set_launch), each closed by the FP64 budget
- * reduction; an odd last step runs eagerly.  Returns LBPC_EINVAL for
+ * to graph_steps steps (lbpc_set_launch; the remainder in a shorter graph),
+ * each closed by the FP64 budget reduction.  Returns LBPC_EINVAL for
  * nsteps < 0 and LBPC_EUNSTABLE, without stepping, once a cavity has been
  * flagged. */
 int lbpc_step(lbpc_ctx* ctx, int64_t nsteps);

@@ -448,9 +448,9 @@ struct lbpc_ctx {
   int pending = 0;
   int64_t steps = 0;
   bool unstable = false;
-  // captured graphs of 2, 4, ..., kRing steps from either state region
-  hipGraphExec_t gexec[2][kRing / 2 + 1] = {};
-  hipGraph_t graph[2][kRing / 2 + 1] = {};
+  // captured graphs of 1 to kRing steps from either state region
+  hipGraphExec_t gexec[2][kRing + 1] = {};
+  hipGraph_t graph[2][kRing + 1] = {};
   std::string err;
   AdjointPlan adj;
 };
@@ -537,7 +537,7 @@ hipError_t reduce(lbpc_ctx* x, const double* partials, int nslots, int mode, hip
 
 void drop_graphs(lbpc_ctx* x) {
   for (int i = 0; i < 2; ++i)
-    for (int k = 0; k <= kRing / 2; ++k) {
+    for (int k = 0; k <= kRing; ++k) {
       // release paths have no caller to report a failure to
       if (x->gexec[i][k]) (void)hipGraphExecDestroy(x->gexec[i][k]);
       if (x->graph[i][k]) (void)hipGraphDestroy(x->graph[i][k]);
@@ -651,8 +651,17 @@ int eager_step(lbpc_ctx* x) {
   return LBPC_OK;
 }
 
-// Capture `count` (even) steps plus their reduction, starting from region `from`.
+// Capture `count` steps plus their reduction, starting from region `from`.
+// The graph's steps walk the queue forward, backward, ... from its first
+// step on, whatever the host-side alternation is at capture time.
 int capture(lbpc_ctx* x, int from, int count) {
+  const int flip = x->flip;
+  x->flip = 0;
+  struct Restore {
+    lbpc_ctx* x;
+    int flip;
+    ~Restore() { x->flip = flip; }
+  } restore{x, flip};
   HIPCHK(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
   int c = from;
   hipError_t e = hipSuccess;
@@ -669,39 +678,42 @@ int capture(lbpc_ctx* x, int from, int count) {
     return fail(x, LBPC_EHIP, std::string("graph capture: ") +
                                   hipGetErrorString(e != hipSuccess ? e : e2));
   }
-  x->graph[from][count / 2] = g;
-  HIPCHK(x, hipGraphInstantiate(&x->gexec[from][count / 2], g, nullptr, nullptr, 0));
+  x->graph[from][count] = g;
+  HIPCHK(x, hipGraphInstantiate(&x->gexec[from][count], g, nullptr, nullptr, 0));
   return LBPC_OK;
 }
 
-// Every graph a run can use (2, 4, ..., graph_steps steps from either
-// region), captured together the first time one is needed, so that capture
-// and instantiation cost no time later in the run.
+// Every graph a run can use (1 to graph_steps steps from either region),
+// captured together the first time one is needed, so that capture and
+// instantiation cost no time later in the run.
 int ensure_graphs(lbpc_ctx* x) {
   for (int from = 0; from < 2; ++from)
-    for (int count = 2; count <= x->graph_steps; count += 2)
-      if (!x->gexec[from][count / 2]) {
+    for (int count = 1; count <= x->graph_steps; ++count)
+      if (!x->gexec[from][count]) {
         const int rc = capture(x, from, count);
         if (rc) return rc;
       }
   return LBPC_OK;
 }
 
-// Steps go into graphs of graph_steps steps, and a shorter even remainder
-// into a graph of its own; partials left by eager steps are reduced first, so
-// every graph starts on an empty ring.  Only an odd last step runs eagerly.
+// Steps go into graphs of graph_steps steps, and the remainder into a graph
+// of its own, each closed by its reduction; partials left by eager steps are
+// reduced first, so every graph starts on an empty ring.  graph_steps = 0
+// runs every step eagerly.
 int run_steps(lbpc_ctx* x, int64_t n) {
   while (n > 0) {
-    if (x->graph_steps > 0 && n >= 2) {
+    if (x->graph_steps > 0) {
       int rc = flush(x);
       if (rc) return rc;
-      const int count = static_cast<int>(std::min<int64_t>(x->graph_steps, n / 2 * 2));
-      if (!x->gexec[x->cur][count / 2]) {
+      const int count = static_cast<int>(std::min<int64_t>(x->graph_steps, n));
+      if (!x->gexec[x->cur][count]) {
         rc = ensure_graphs(x);
         if (rc) return rc;
       }
-      HIPCHK(x, hipGraphLaunch(x->gexec[x->cur][count / 2], x->stream));
+      HIPCHK(x, hipGraphLaunch(x->gexec[x->cur][count], x->stream));
       x->steps += count;
+      x->cur ^= count & 1;
+      x->flip = count & 1;  // the next step walks against the graph's last one
       n -= count;
     } else {
       const int rc = eager_step(x);
