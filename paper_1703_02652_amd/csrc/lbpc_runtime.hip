@@ -482,8 +482,8 @@ hipError_t dispatch_step(lbpc_ctx* x, const char* src, char* dst, double* partia
   a.partials = partials;
   a.status = x->d_status;
   a.budget = budget;
-  // consecutive steps walk the tile queue in opposite directions (graphs hold
-  // an even number of steps, so replays keep the alternation)
+  // consecutive steps walk the tile queue in opposite directions (a captured
+  // graph starts forward and alternates from there; see capture)
   a.reverse = x->flip;
   x->flip ^= 1;
   a.block = x->block;

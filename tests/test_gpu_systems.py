@@ -100,10 +100,12 @@ def test_graph_replays_match_eager_steps_every_replay():
 
 
 def test_graph_remainders_and_pending_partials_match_eager_steps():
-    """Five eager steps leave partials in the ring; 20 more steps then reduce
-    them and run as a 16-step and a 4-step graph.  State and budgets equal 25
-    steps launched one by one, bit for bit, and the same again after 13 more
-    (a 12-step graph and one eager step)."""
+    """Graphs of every length against eager steps: five 1-step graphs, then 20
+    steps as a 16-step and a 4-step graph, then 13 more as a 12-step and a
+    1-step graph (each graph closed by its reduction, walking the queue
+    forward from its first step).  State and budgets equal the same steps
+    launched one by one, with the partials of up to 16 reduced together, bit
+    for bit."""
     cfg = W.melting_cavity(24, 1e5, 0.02, 0.1, precision=W.FP32)
     cfg.update(ny=17, nz=11)
     walls = {0: W.hot_wall_field(17, 11)}
