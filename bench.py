@@ -353,6 +353,7 @@ def main():
         print(f"bench.py: the lbpc library runs on one GPU (asked for --gpus {args.gpus}); "
               "a multi-GPU decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
@@ -409,68 +410,86 @@ def main():
     del cav
 
     extras = {}
+
+    def extra(key, fn, *a, **kw):
+        """One extra figure: a failure is logged and recorded under its key, so
+        that it never costs the main line."""
+        try:
+            val = fn(*a, **kw)
+        except Exception as e:  # noqa: BLE001 - any failure of a side figure
+            val = {"error": f"{type(e).__name__}: {e}"}
+        finally:
+            torch.cuda.empty_cache()
+        if isinstance(val, dict) and key is None:
+            extras.update(val)
+        else:
+            extras[key] = val
+        log(f"[bench] {key or fn.__name__}: {val}")
+
+    def cavity256(xprec, xs):
+        c = W.precision_cavity(256, 0.02, precision=xprec)
+        cv, r = run_cavity(c, xs, 20, label=f"cavity256 precision {xprec}")
+        try:
+            r["hbm_frac"] = round(BYTES_PER_CELL[xprec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
+                                  / HBM_PEAK_GBS, 4)
+        finally:
+            cv.close()
+        return r
+
+    def table2(case, xs):
+        c = W.table2_case(case)
+        cv, r = run_cavity(c, xs, 20, label=f"table2 case {case}")
+        try:
+            cv.step(200)
+            b = cv.budgets()[0]
+            r["after_steps"] = int(b[4])
+            r["nusselt_hot_wall"] = round(float(cv.nusselt()), 4)
+            r["mean_fl"] = round(float(b[2]) / (c["nx"] * c["ny"] * c["nz"]), 6)
+        finally:
+            cv.close()
+        return r
+
+    def batch64():
+        from paper_1703_02652_amd import Cavity
+        bcfgs, _ = W.batch_cavities()
+        bc = Cavity(bcfgs, device="cuda")
+        try:
+            bc.autotune(5)
+            bc.step(20)
+            bsteps = 5000   # the whole run of the batch workload, timed in one call
+            dt = timed_steps(bc, bsteps)
+            cells = np.array([c["nx"] * c["ny"] * c["nz"] for c in bcfgs], dtype=np.float64)
+            bb = bc.budgets()
+            fl = bb[:, 2] / cells
+            return dict(cells=int(cells.sum()), steps=bsteps,
+                        mlups=float(cells.sum()) * bsteps / dt / 1e6, ms_per_step=1e3 * dt / bsteps,
+                        launch=list(bc.get_launch()), unstable_cavities=int(bc.status().sum()),
+                        mean_fl_min=round(float(fl.min()), 6), mean_fl_max=round(float(fl.max()), 6))
+        finally:
+            bc.close()
+
     if not args.no_extras:
         xs = max(50, args.steps // 5)
         for name, xprec in (("cavity256_fp32", W.FP32), ("cavity256_fp16s", W.FP16S),
                             ("cavity256_bf16s", W.BF16S)):
-            c = W.precision_cavity(256, 0.02, precision=xprec)
-            cv, r = run_cavity(c, xs, 20, label=name)
-            r["hbm_frac"] = round(BYTES_PER_CELL[xprec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
-                                  / HBM_PEAK_GBS, 4)
-            extras[name] = r
-            cv.close()
-            del cv
-            torch.cuda.empty_cache()
+            extra(name, cavity256, xprec, xs)
         for case in (1, 2, 3):
-            c = W.table2_case(case)
-            cv, r = run_cavity(c, xs, 20, label=f"table2 case {case}")
-            cv.step(200)
-            r["after_steps"] = int(cv.budgets()[0, 4])
-            r["nusselt_hot_wall"] = round(float(cv.nusselt()), 4)
-            r["mean_fl"] = round(float(cv.budgets()[0, 2]) / (c["nx"] * c["ny"] * c["nz"]), 6)
-            extras[f"table2_case{case}_fp32"] = r
-            cv.close()
-            del cv
-        extras["table2_case1_history_fp32"] = table2_history()
-        log(f"[bench] table 2 case 1 history: {extras['table2_case1_history_fp32']}")
-        from paper_1703_02652_amd import Cavity
-        bcfgs, _ = W.batch_cavities()
-        bc = Cavity(bcfgs, device="cuda")
-        bc.autotune(5)
-        bc.step(20)
-        bsteps = 5000   # the whole run of the batch workload, timed in one call
-        dt = timed_steps(bc, bsteps)
-        bcells = sum(c["nx"] * c["ny"] * c["nz"] for c in bcfgs)
-        bb = bc.budgets()
-        extras["batch64_fp32"] = dict(cells=bcells, steps=bsteps, mlups=bcells * bsteps / dt / 1e6,
-                                      ms_per_step=1e3 * dt / bsteps, launch=list(bc.get_launch()),
-                                      unstable_cavities=int(bc.status().sum()),
-                                      mean_fl_min=round(float((bb[:, 2] / [c["nx"] * c["ny"] * c["nz"] for c in bcfgs]).min()), 6),
-                                      mean_fl_max=round(float((bb[:, 2] / [c["nx"] * c["ny"] * c["nz"] for c in bcfgs]).max()), 6))
-        log(f"[bench] batch64: {extras['batch64_fp32']}")
-        bc.close()
-        del bc
-        torch.cuda.empty_cache()
-        extras["precision256_errors"] = precision_errors()
-        log(f"[bench] precision errors: {extras['precision256_errors']}")
-        extras["adjoint96_fp32"] = adjoint_ratio(W.FP32)
-        log(f"[bench] adjoint fp32: {extras['adjoint96_fp32']}")
-        extras["adjoint96_fp64"] = adjoint_ratio(W.FP64)
-        log(f"[bench] adjoint fp64: {extras['adjoint96_fp64']}")
-        extras["cavity128_full_run_fp32"] = full_run_128(main_r["launch"])
-        log(f"[bench] 128^3 full run: {extras['cavity128_full_run_fp32']}")
-        extras["adjoint96_fp32_every_step"] = adjoint_ratio(W.FP32, steps=200, every=1)
-        log(f"[bench] adjoint fp32, a snapshot per step: {extras['adjoint96_fp32_every_step']}")
-        extras.update(two_d_validations())
-        log(f"[bench] 2D: {extras['corner400_fp32']} {extras['convection2d128_fp32']}")
+            extra(f"table2_case{case}_fp32", table2, case, xs)
+        extra("table2_case1_history_fp32", table2_history)
+        extra("batch64_fp32", batch64)
+        extra("precision256_errors", precision_errors)
+        extra("adjoint96_fp32", adjoint_ratio, W.FP32)
+        extra("adjoint96_fp64", adjoint_ratio, W.FP64)
+        extra("cavity128_full_run_fp32", full_run_128, main_r["launch"])
+        extra("adjoint96_fp32_every_step", adjoint_ratio, W.FP32, steps=200, every=1)
+        extra(None, two_d_validations)
 
     cpu = None
     if not args.no_cpu and not isinstance(cfg, list):
         cpu = cpu_baseline(dict(cfg, precision=W.FP64))
         log(f"[bench] cpu baseline: {cpu}")
         if not args.no_extras:
-            extras["cpu_oracle_scaled"] = cpu_scaled()
-            log(f"[bench] cpu scaled: {extras['cpu_oracle_scaled']}")
+            extra("cpu_oracle_scaled", cpu_scaled)
 
     out = dict(
         metric=f"coupled flow+enthalpy MLUPS ({args.workload})",
