@@ -237,8 +237,10 @@ int lbpc_time_step_kernel(lbpc_ctx* ctx, int32_t nsteps, double* host_ms_out);
  *     goes to host_loss (synchronises).  ckpt_every = 1 keeps every state
  *     (nsteps regions: 96^3 x 2000 FP32 steps take 191 GB): each step writes
  *     into its snapshot directly and the reverse sweep recomputes nothing.
- *   lbpc_adjoint_backward: reverse sweep with recomputation per segment; seed
- *     scales the loss (dL/dL = seed).  dev_dL_dTw: FP64, all six faces'
+ *   lbpc_adjoint_backward: reverse sweep with recomputation per segment (the
+ *     forward run leaves the states of its last segment in place, so the first
+ *     call recomputes every segment but that one); seed scales the loss
+ *     (dL/dL = seed); it may be called again for the same forward run.  dev_dL_dTw: FP64, all six faces'
  *     node fields back to back (layout of lbpc_set_wall_T), zero on faces
  *     that are not fixed-temperature.  dev_dL_dT0: FP64 per cell, the
  *     derivative w.r.t. the initial temperature of lbpc_create (one-sided,

@@ -417,6 +417,7 @@ struct AdjointPlan {
   int64_t nsteps = 0, end_step = 0;
   int32_t every = 0, loss = 0;
   int nsnap = 0;
+  bool last_seg_kept = false;  // the forward run left the last segment's states in place
   size_t o_snap = 0, o_seg = 0, o_lam0 = 0, o_lam1 = 0, o_dtw = 0, o_part = 0, total = 0;
   size_t lam_bytes = 0;
 };
@@ -1371,8 +1372,29 @@ int lbpc_adjoint_forward(lbpc_ctx* x, int64_t nsteps, int32_t every, int32_t los
     for (int64_t s = 0; s < nsteps; s += every) {
       HIPCHK(x, hipMemcpyAsync(a.ws + a.o_snap + rb * static_cast<size_t>(s / every),
                                x->region[x->cur], rb, hipMemcpyDeviceToDevice, x->stream));
-      rc = run_steps(x, std::min<int64_t>(every, nsteps - s));
-      if (rc) return rc;
+      const int64_t len = std::min<int64_t>(every, nsteps - s);
+      if (s + len < nsteps) {
+        rc = run_steps(x, len);
+        if (rc) return rc;
+        continue;
+      }
+      // the last segment writes its states straight into the recomputation
+      // slots, so that the backward sweep starts without recomputing it
+      char* seg = a.ws + a.o_seg;
+      for (int64_t t = 0; t < len; ++t) {
+        const char* src = t == 0 ? x->region[x->cur] : seg + rb * static_cast<size_t>(t - 1);
+        char* dst = t + 1 < len ? seg + rb * static_cast<size_t>(t) : x->region[x->cur ^ 1];
+        double* part = x->d_part + static_cast<int64_t>(x->pending) * x->L.max_waves;
+        const int budget = (x->pending + 1 == kRing || t + 1 == len) ? 2 : 1;
+        HIPCHK(x, dispatch_step(x, src, dst, part, budget, x->stream));
+        x->steps += 1;
+        if (++x->pending == kRing) {
+          rc = flush(x);
+          if (rc) return rc;
+        }
+      }
+      x->cur ^= 1;
+      a.last_seg_kept = true;
     }
   }
   a.end_step = x->steps;
@@ -1416,7 +1438,10 @@ int lbpc_adjoint_backward(lbpc_ctx* x, double seed, double* dev_dL_dTw, double* 
     const int64_t t0 = static_cast<int64_t>(seg) * a.every;
     const int64_t t1 = std::min<int64_t>(t0 + a.every, a.nsteps);
     // recompute the states t0+1 .. t1-1 of this segment from its snapshot
-    for (int64_t t = t0; t + 1 < t1; ++t)
+    // (the forward run left those of the last segment in place)
+    const bool kept = seg == a.nsnap - 1 && a.last_seg_kept;
+    if (!kept && t1 - t0 > 1) a.last_seg_kept = false;  // the slots now hold another segment
+    for (int64_t t = t0; !kept && t + 1 < t1; ++t)
       HIPCHK(x, dispatch_step(x, state_at(t, t0), state_at(t + 1, t0), nullptr, 0, x->stream));
     for (int64_t t = t1 - 1; t >= t0; --t) {
       AdjArgs g;
