@@ -73,3 +73,60 @@ def test_cavity256_full_size_one_step_against_oracle(prec):
     assert ef < 2.0 ** -bits * dev + floor
     assert eg < 2.0 ** -bits * np.abs(ref[1][1:]).max()
     assert abs(cav.budgets()[0, 1] / 256**3 - 1.0) < 1e-5
+
+
+# (flow, enthalpy model, faces) on a ragged 13 x 11 x 9 lattice: walls only,
+# mixed walls and periodic pairs, fully periodic
+FORMAT_CASES = [
+    (1, W.MRT, [D, D, A, A, A, A]),
+    (1, W.SRT, [D, A, P, P, D, A]),
+    (1, W.MRT, [P] * 6),
+    (0, W.MRT, [D, A, P, P, P, P]),
+    (1, W.MRT, [A, D, D, A, D, D]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FORMAT_CASES)))
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16S, W.BF16S])
+def test_random_state_one_step_in_every_storage_format(case, prec):
+    """One step from an arbitrary state held in FP32, shifted FP16 or shifted
+    BF16 storage (per-node wall temperatures; the 16-bit formats with a
+    reference temperature of 0.3) against the oracle's FP64 step from the same
+    decoded state: each population plane within the storage rounding of its
+    own deviation from rest (f - w rho0, g_a - (omega_T / 2) C_p,ref T_shift)
+    plus FP32 arithmetic on the largest deviation."""
+    flow, model, bc = FORMAT_CASES[case]
+    t_shift = 0.3 if prec in (W.FP16S, W.BF16S) else 0.0
+    cfg = W.base_config(13, 11, 9, flow=flow, enth_model=model, precision=prec, face_bc=list(bc),
+                        face_T=[1.0, -0.4, 0.3, 0.7, 0.9, -0.2], g_beta=4e-3, latent=1.5,
+                        lambda_s=0.09, lambda_l=0.09, nu=0.04, T_shift=t_shift)
+    f, g = W.random_populations(cfg, seed=500 + case, f_scale=W19)
+    walls = random_walls(cfg, seed=600 + case)
+    tw = W.wall_fields(cfg, walls)
+    cav = make_cavity(cfg, walls=walls)
+    cav.set_state(f, g)
+    f0, g0 = cav.state()               # the stored state, decoded
+    st = (f0.cpu().numpy() if flow else None, g0.cpu().numpy())
+    cav.step(1)
+    f1, g1 = cav.state()
+    ref = oracle.run(dict(cfg, precision=W.FP64), st, 1, tw=tw)
+    bits = {W.FP32: 20, W.FP16S: 10, W.BF16S: 7}[prec]
+    floor = 2.0 ** -24 if prec == W.FP16S else 0.0   # FP16 subnormal spacing
+    worst = 0.0
+    if flow:
+        rest = W19.reshape(19, 1, 1, 1) * cfg["rho0"]
+        dev = np.abs(ref[0] - rest).reshape(19, -1).max(axis=1)
+        err = np.abs(f1.cpu().numpy() - ref[0]).reshape(19, -1).max(axis=1)
+        bound = 2.0 ** -bits * dev + 2.0 ** -18 * dev.max() + floor
+        worst = max(worst, float((err / bound).max()))
+        assert (err < bound).all(), (err, bound)
+    gshift = 0.5 * cfg["omega_T"] * cfg["cp_ref"] * t_shift
+    gdev = np.abs(ref[1][1:] - gshift).reshape(6, -1).max(axis=1)
+    gerr = np.abs(g1.cpu().numpy()[1:] - ref[1][1:]).reshape(6, -1).max(axis=1)
+    gbound = 2.0 ** -bits * gdev + 2.0 ** -18 * gdev.max() + floor
+    e0 = absdiff(g1[0], ref[1][0])
+    b0 = 2.0 ** -22 * np.abs(ref[1][0]).max() + 2.0 ** -18 * gdev.max()
+    worst = max(worst, float((gerr / gbound).max()), e0 / b0)
+    print(f"case {case} {['fp64', 'fp32', 'fp16s', 'bf16s'][prec]}: largest error / bound {worst:.3f}")
+    assert (gerr < gbound).all(), (gerr, gbound)
+    assert e0 < b0
