@@ -1246,7 +1246,7 @@ int lbpc_autotune(lbpc_ctx* x, int32_t trial_steps, double* host_ms_out) {
     return LBPC_OK;
   };
   // stage 1: every shape once; stage 2: the three fastest again, interleaved,
-  // four rounds each (a drift of the box then hits all three alike)
+  // four rounds each (a drift of the device clock then hits all three alike)
   Cand best{x->block, x->grid, x->xrun, 0.0};
   auto tune = [&]() -> int {
     std::vector<Cand> cands;
