@@ -188,7 +188,7 @@ int lbpc_load(lbpc_ctx* ctx, const void* host_buf, size_t bytes);
 /* Launch configuration.  block: threads (and cells) per tile, 64, 128, 192
  * or 256; grid_blocks: 0 for one workgroup per tile, else a persistent
  * grid (rounded up to a multiple of 8) that strides over the tile queue;
- * graph_steps: steps per captured HIP graph (even, at most 16, 0 disables
+ * graph_steps: steps per captured HIP graph (at most 16, 0 disables
  * graphs); xcd_run: 0..2^24, the queue order.  The MI355X dispatcher sends
  * workgroup b to XCD b mod 8; for xcd_run >= 1 the queue is ordered so that
  * each XCD walks runs of xcd_run consecutive tiles (in the natural order of

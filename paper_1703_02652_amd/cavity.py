@@ -176,7 +176,7 @@ class Cavity:
     # ------------------------------------------------------ launch shapes
     def set_launch(self, block=256, grid=0, graph_steps=16, xcd_run=4):
         """block: cells per tile (64..256); grid: 0 for one workgroup per tile,
-        else a persistent grid; graph_steps: steps per HIP graph (even, <= 16);
+        else a persistent grid; graph_steps: steps per HIP graph (<= 16, 0 none);
         xcd_run: tiles per XCD run of the queue (1 natural order), 0 for one
         y-block of every slab per XCD (see lbpc_set_launch)."""
         self._check(self._L.lbpc_set_launch(self._ctx, block, grid, graph_steps, xcd_run))

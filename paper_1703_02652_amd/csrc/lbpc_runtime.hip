@@ -1111,8 +1111,8 @@ int lbpc_set_launch(lbpc_ctx* x, int32_t block, int32_t grid_blocks, int32_t gra
   if (block < kMinTile || block > kMaxTile || block % 64)
     return fail(x, LBPC_EINVAL, "block must be 64, 128, 192 or 256");
   if (grid_blocks < 0) return fail(x, LBPC_EINVAL, "grid_blocks must be >= 0");
-  if (graph_steps < 0 || graph_steps > kRing || graph_steps % 2)
-    return fail(x, LBPC_EINVAL, "graph_steps must be even and <= 16");
+  if (graph_steps < 0 || graph_steps > kRing)
+    return fail(x, LBPC_EINVAL, "graph_steps must lie in [0, 16]");
   if (xcd_run < 0 || xcd_run > kMaxRun) return fail(x, LBPC_EINVAL, "xcd_run must lie in [0, 2^24]");
   int rc = flush(x);
   if (rc) return rc;

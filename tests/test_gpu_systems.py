@@ -101,30 +101,36 @@ def test_graph_replays_match_eager_steps_every_replay():
 
 def test_graph_remainders_and_pending_partials_match_eager_steps():
     """Graphs of every length against eager steps: five 1-step graphs, then 20
-    steps as a 16-step and a 4-step graph, then 13 more as a 12-step and a
-    1-step graph (each graph closed by its reduction, walking the queue
-    forward from its first step).  State and budgets equal the same steps
-    launched one by one, with the partials of up to 16 reduced together, bit
-    for bit."""
+    steps as a 16-step and a 4-step graph, then 13 more as one 13-step graph
+    (each graph closed by its reduction, walking the queue forward from its
+    first step); and with graphs of at most 5 steps (an odd length), the same
+    25 + 13 steps as graphs of 5, 5, 5, 5, 5 and 5, 5, 3.  State and budgets
+    equal the same steps launched one by one, with the partials of up to 16
+    reduced together, bit for bit."""
     cfg = W.melting_cavity(24, 1e5, 0.02, 0.1, precision=W.FP32)
     cfg.update(ny=17, nz=11)
     walls = {0: W.hot_wall_field(17, 11)}
     g = make_cavity(cfg, walls=walls)
+    o = make_cavity(cfg, walls=walls)
     e = make_cavity(cfg, walls=walls)
     g.set_launch(256, 0, 16, 4)
+    o.set_launch(256, 0, 5, 4)
     e.set_launch(256, 0, 0, 4)
     for _ in range(5):
         g.step(1)
     g.step(20)
+    o.step(25)
     e.step(25)
     for more in (0, 13):
         g.step(more)
+        o.step(more)
         e.step(more)
-        bg, be = g.budgets(), e.budgets()
-        for x, y in zip(_state_bytes(g), _state_bytes(e)):
-            assert np.array_equal(x, y), more
-        assert np.array_equal(bg, be), more
-    assert bg[0, 4] == 38
+        be = e.budgets()
+        for c in (g, o):
+            for x, y in zip(_state_bytes(c), _state_bytes(e)):
+                assert np.array_equal(x, y), more
+            assert np.array_equal(c.budgets(), be), more
+    assert be[0, 4] == 38
 
 
 @pytest.mark.parametrize("n", [32, 128])
@@ -210,7 +216,9 @@ def test_invalid_arguments_raise():
     with pytest.raises(LbpcError):
         cav.set_launch(100, 0, 16)
     with pytest.raises(LbpcError):
-        cav.set_launch(256, 0, 3)
+        cav.set_launch(256, 0, 17)     # graphs of at most 16 steps (the budget ring)
+    with pytest.raises(LbpcError):
+        cav.set_launch(256, 0, -1)
     with pytest.raises(LbpcError):
         cav.set_launch(256, 0, 16, -1)
     with pytest.raises(LbpcError):
