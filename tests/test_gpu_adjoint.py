@@ -236,6 +236,30 @@ def test_adjoint_with_a_snapshot_of_every_step_equals_segments():
     assert np.abs(d1).max() > 1e-3
 
 
+@pytest.mark.parametrize("nsteps,every", [(1, 100), (5, 100), (7, 7), (8, 7)])
+def test_short_runs_and_segment_edges_equal_a_snapshot_per_step(nsteps, every):
+    """Edge cases of the checkpointed adjoint: one step, a run shorter than a
+    segment (the forward run leaves all its states for the reverse sweep), a
+    last segment that ends on the final step, and a last segment of one step:
+    loss, final state and gradients equal those with a snapshot of every step,
+    bit for bit (FP64)."""
+    cfg = W.melting_cavity(10, 1e5, 0.5, 0.2, precision=W.FP64)
+    cfg.update(ny=8, nz=7)
+    walls = {0: W.hot_wall_field(8, 7)}
+    out = []
+    for k in (every, 1):
+        cav = make_cavity(cfg, walls=walls)
+        cav.step(30)     # a melted layer, so that the gradients are not zero
+        L = cav.adjoint_forward(nsteps, k)
+        dtw, _ = cav.adjoint_backward()
+        out.append((L, dtw.cpu().numpy(), cav.state()[1].cpu().numpy()))
+    (La, da, ga), (Lb, db, gb) = out
+    assert La == Lb
+    assert np.array_equal(ga, gb)
+    assert np.array_equal(da, db)
+    assert np.abs(da).max() > 0.0
+
+
 @pytest.mark.parametrize("every", [7, 9])
 def test_backward_twice_gives_the_same_gradients(every):
     """The first reverse sweep uses the last segment's states as the forward
