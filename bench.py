@@ -426,12 +426,12 @@ def main():
             extras[key] = val
         log(f"[bench] {key or fn.__name__}: {val}")
 
-    def cavity256(xprec, xs):
-        c = W.precision_cavity(256, 0.02, precision=xprec)
-        cv, r = run_cavity(c, xs, 20, label=f"cavity256 precision {xprec}")
+    def cavity_extra(c, xs, label):
+        cv, r = run_cavity(c, xs, 20, label=label)
         try:
-            r["hbm_frac"] = round(BYTES_PER_CELL[xprec] * 256**3 / (r["kernel_ms"] * 1e-3) / 1e9
-                                  / HBM_PEAK_GBS, 4)
+            n = c["nx"] * c["ny"] * c["nz"]
+            r["hbm_frac"] = round(BYTES_PER_CELL[c["precision"]] * n / (r["kernel_ms"] * 1e-3)
+                                  / 1e9 / HBM_PEAK_GBS, 4)
         finally:
             cv.close()
         return r
@@ -472,7 +472,8 @@ def main():
         xs = max(50, args.steps // 5)
         for name, xprec in (("cavity256_fp32", W.FP32), ("cavity256_fp16s", W.FP16S),
                             ("cavity256_bf16s", W.BF16S)):
-            extra(name, cavity256, xprec, xs)
+            extra(name, cavity_extra, W.precision_cavity(256, 0.02, precision=xprec), xs, name)
+        extra("cavity128_fp64", cavity_extra, W.cavity_128(precision=W.FP64), xs, "cavity128_fp64")
         for case in (1, 2, 3):
             extra(f"table2_case{case}_fp32", table2, case, xs)
         extra("table2_case1_history_fp32", table2_history)

@@ -230,6 +230,16 @@ def test_invalid_arguments_raise():
     c16cav = Cavity(c16, device="cuda")
     with pytest.raises(LbpcError):
         c16cav.adjoint_forward(10, 5)
+    # checkpoints: a truncated buffer, and one from a context of another layout
+    blob = cav.save()
+    with pytest.raises(LbpcError):
+        cav.load(blob[:-1])
+    with pytest.raises(LbpcError):
+        c16cav.load(blob[:len(c16cav.save())])
+    other = Cavity(dict(cfg, nx=9), device="cuda")
+    with pytest.raises(LbpcError):
+        other.load(blob + bytes(len(other.save())))
+    cav.load(blob)                      # the matching context takes it back
 
 
 @pytest.mark.parametrize("prec", [W.FP16S, W.BF16S])
