@@ -8,7 +8,8 @@ rounding differences grow pointwise over a long run (over all cells: 3.9e-6
 at step 10,000, 6.8e-6 at 12,000, 8.5e-5 at 20,000): the liquid fraction of
 the sampled cells is held to 1e-5 for the first 12,000 steps, and the mean
 liquid fraction (to 1e-6; observed 1.8e-8) and the hot-wall Nusselt number of
-Eq. (65) (to 1e-5 relative; observed 8.3e-7) over the whole run."""
+Eq. (65) (to 1e-5 relative; observed 8.3e-7) over the whole run.  The same run
+in the 16-bit storage formats is reported against the same record."""
 import json
 import os
 
@@ -51,3 +52,29 @@ def test_cavity128_fp32_whole_run_against_the_oracle():
     assert worst_cells_young < 1e-5
     assert worst_mean < 1e-6
     assert worst_nu < 1e-5
+
+
+@pytest.mark.parametrize("prec", [W.FP16S, W.BF16S])
+def test_cavity128_sixteen_bit_whole_run_against_the_oracle(prec):
+    """The same 20,000 steps in shifted FP16 or BF16 storage (reference
+    temperature 0.5) against the stored FP64 oracle run: reported (largest
+    difference of the mean liquid fraction, of the hot-wall Nusselt number and
+    at the sampled cells), with loose bounds that only catch a broken format."""
+    doc = json.load(open(GOLDEN))
+    n, every = doc["n"], doc["every"]
+    cells = np.array(doc["cells"])
+    cav = make_cavity(W.cavity_128(precision=prec))
+    cav.autotune(3)
+    worst_mean, worst_nu, worst_cells = 0.0, 0.0, 0.0
+    for s in doc["samples"]:
+        cav.step(every)
+        b = cav.budgets()[0]
+        fl = cav.fields(names=("fl",))["fl"].reshape(-1)[cells].cpu().numpy()
+        worst_mean = max(worst_mean, abs(b[2] / n**3 - s["mean_fl"]))
+        worst_nu = max(worst_nu, abs(b[6] / s["nusselt"] - 1.0))
+        worst_cells = max(worst_cells, float(np.abs(fl - np.array(s["fl"])).max()))
+    name = {W.FP16S: "fp16s", W.BF16S: "bf16s"}[prec]
+    print(f"{name} over 20,000 steps: |d mean f_l| {worst_mean:.1e}, Nu rel {worst_nu:.1e}, "
+          f"sampled cells |d f_l| {worst_cells:.1e}")
+    assert cav.status().max() == 0
+    assert worst_mean < 0.02 and worst_nu < 0.1
