@@ -1,15 +1,16 @@
-"""The whole 128^3 workload (Ra 1e5, Pr 0.02, Ste 0.1, 20,000 steps, FP32)
-on the GPU against the FP64 oracle's run of it, stored in
-tests/golden/cavity128_oracle.json by tests/golden/make_cavity128_golden.py
-(oracle only; about 90 minutes of host time, so it is not rerun here).
+"""Long runs on the GPU against FP64 oracle runs stored in tests/golden/ by
+tests/golden/make_cavity128_golden.py (oracle only; 90 and 30 minutes of host
+time, so they are not rerun here).
 
-The flow at these parameters is unsteady (Sec. 3.3), so FP32 and FP64
-rounding differences grow pointwise over a long run (over all cells: 3.9e-6
-at step 10,000, 6.8e-6 at 12,000, 8.5e-5 at 20,000): the liquid fraction of
-the sampled cells is held to 1e-5 for the first 12,000 steps, and the mean
-liquid fraction (to 1e-6; observed 1.8e-8) and the hot-wall Nusselt number of
+The whole 128^3 workload (Ra 1e5, Pr 0.02, Ste 0.1, 20,000 steps, FP32): the
+flow at these parameters is unsteady (Sec. 3.3), so FP32 and FP64 rounding
+differences grow pointwise over a long run (over all cells: 3.9e-6 at step
+10,000, 6.8e-6 at 12,000, 8.5e-5 at 20,000): the liquid fraction of the
+sampled cells is held to 1e-5 for the first 12,000 steps, and the mean liquid
+fraction (to 1e-6; observed 1.8e-8) and the hot-wall Nusselt number of
 Eq. (65) (to 1e-5 relative; observed 8.3e-7) over the whole run.  The same run
-in the 16-bit storage formats is reported against the same record."""
+in the 16-bit storage formats is reported against the same record.  Case 1 of
+Table 2 on its own grid over 6000 FP32 steps against its record."""
 import json
 import os
 
@@ -22,6 +23,8 @@ from gpu_util import make_cavity
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cavity128_oracle.json")
+GOLDEN_T2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "table2_case1_oracle.json")
 
 
 def test_cavity128_fp32_whole_run_against_the_oracle():
@@ -78,3 +81,31 @@ def test_cavity128_sixteen_bit_whole_run_against_the_oracle(prec):
           f"sampled cells |d f_l| {worst_cells:.1e}")
     assert cav.status().max() == 0
     assert worst_mean < 0.02 and worst_nu < 0.1
+
+
+def test_table2_case1_fp32_against_the_oracle():
+    """Case 1 of Table 2 (160 x 160 x 80, Ra 2.5e4, Pr 0.02, Ste 0.4), 6000 FP32
+    steps, every 1000 steps: the liquid fraction at the sampled cells (1e-5),
+    the mean liquid fraction and the hot-wall Nusselt number of Eq. (65)
+    against the stored FP64 oracle run."""
+    doc = json.load(open(GOLDEN_T2))
+    every, cells = doc["every"], np.array(doc["cells"])
+    cfg = W.table2_case(1, precision=W.FP32)
+    assert doc["shape"] == [cfg["nx"], cfg["ny"], cfg["nz"]]
+    ncell = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    cav = make_cavity(cfg)
+    cav.autotune(3)
+    worst_mean, worst_nu, worst_cells = 0.0, 0.0, 0.0
+    for s in doc["samples"]:
+        cav.step(every)
+        b = cav.budgets()[0]
+        assert b[4] == s["step"]
+        fl = cav.fields(names=("fl",))["fl"].reshape(-1)[cells].cpu().numpy()
+        worst_mean = max(worst_mean, abs(b[2] / ncell - s["mean_fl"]))
+        worst_nu = max(worst_nu, abs(b[6] / s["nusselt"] - 1.0))
+        worst_cells = max(worst_cells, float(np.abs(fl - np.array(s["fl"])).max()))
+    print(f"Table 2 case 1 over {doc['samples'][-1]['step']} steps: |d mean f_l| {worst_mean:.1e}, "
+          f"Nu rel {worst_nu:.1e}, sampled cells |d f_l| {worst_cells:.1e}")
+    assert worst_cells < 1e-5
+    assert worst_mean < 1e-6
+    assert worst_nu < 1e-5
