@@ -75,6 +75,29 @@ def test_cavity256_full_size_one_step_against_oracle(prec):
     assert abs(cav.budgets()[0, 1] / 256**3 - 1.0) < 1e-5
 
 
+def _storage_step_error(cfg, prec, flow, t_shift, f1, g1, ref):
+    """Largest ratio of error to bound after one step in a storage format:
+    each population plane within the storage rounding of its own deviation
+    from rest (f - w rho0, g_a - (omega_T / 2) C_p,ref T_shift) plus FP32
+    arithmetic on the largest deviation; g_0 within its own FP32 rounding."""
+    bits = {W.FP32: 20, W.FP16S: 10, W.BF16S: 7}[prec]
+    floor = 2.0 ** -24 if prec == W.FP16S else 0.0   # FP16 subnormal spacing
+    worst = 0.0
+    if flow:
+        rest = W19.reshape(19, 1, 1, 1) * cfg["rho0"]
+        dev = np.abs(ref[0] - rest).reshape(19, -1).max(axis=1)
+        err = np.abs(f1.cpu().numpy() - ref[0]).reshape(19, -1).max(axis=1)
+        bound = 2.0 ** -bits * dev + 2.0 ** -18 * dev.max() + floor
+        worst = max(worst, float((err / bound).max()))
+    gshift = 0.5 * cfg["omega_T"] * cfg["cp_ref"] * t_shift
+    gdev = np.abs(ref[1][1:] - gshift).reshape(6, -1).max(axis=1)
+    gerr = np.abs(g1.cpu().numpy()[1:] - ref[1][1:]).reshape(6, -1).max(axis=1)
+    gbound = 2.0 ** -bits * gdev + 2.0 ** -18 * gdev.max() + floor
+    e0 = absdiff(g1[0], ref[1][0])
+    b0 = 2.0 ** -22 * np.abs(ref[1][0]).max() + 2.0 ** -18 * gdev.max()
+    return max(worst, float((gerr / gbound).max()), e0 / b0)
+
+
 # (flow, enthalpy model, faces) on a ragged 13 x 11 x 9 lattice: walls only,
 # mixed walls and periodic pairs, fully periodic
 FORMAT_CASES = [
@@ -110,26 +133,9 @@ def test_random_state_one_step_in_every_storage_format(case, prec):
     cav.step(1)
     f1, g1 = cav.state()
     ref = oracle.run(dict(cfg, precision=W.FP64), st, 1, tw=tw)
-    bits = {W.FP32: 20, W.FP16S: 10, W.BF16S: 7}[prec]
-    floor = 2.0 ** -24 if prec == W.FP16S else 0.0   # FP16 subnormal spacing
-    worst = 0.0
-    if flow:
-        rest = W19.reshape(19, 1, 1, 1) * cfg["rho0"]
-        dev = np.abs(ref[0] - rest).reshape(19, -1).max(axis=1)
-        err = np.abs(f1.cpu().numpy() - ref[0]).reshape(19, -1).max(axis=1)
-        bound = 2.0 ** -bits * dev + 2.0 ** -18 * dev.max() + floor
-        worst = max(worst, float((err / bound).max()))
-        assert (err < bound).all(), (err, bound)
-    gshift = 0.5 * cfg["omega_T"] * cfg["cp_ref"] * t_shift
-    gdev = np.abs(ref[1][1:] - gshift).reshape(6, -1).max(axis=1)
-    gerr = np.abs(g1.cpu().numpy()[1:] - ref[1][1:]).reshape(6, -1).max(axis=1)
-    gbound = 2.0 ** -bits * gdev + 2.0 ** -18 * gdev.max() + floor
-    e0 = absdiff(g1[0], ref[1][0])
-    b0 = 2.0 ** -22 * np.abs(ref[1][0]).max() + 2.0 ** -18 * gdev.max()
-    worst = max(worst, float((gerr / gbound).max()), e0 / b0)
+    worst = _storage_step_error(cfg, prec, flow, t_shift, f1, g1, ref)
     print(f"case {case} {['fp64', 'fp32', 'fp16s', 'bf16s'][prec]}: largest error / bound {worst:.3f}")
-    assert (gerr < gbound).all(), (gerr, gbound)
-    assert e0 < b0
+    assert worst < 1.0
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -169,3 +175,45 @@ def test_random_shapes_faces_and_launches_match_oracle(seed):
     assert rel(gg, st[1]) < 1e-12
     if flow:
         assert rel(fg, st[0]) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(9))
+def test_random_shapes_in_storage_formats_one_step(seed):
+    """Seeded sweep in the FP32, FP16 and BF16 storage formats: random lattice
+    dimensions (1 to 40), face types, flow, enthalpy model and launch shape;
+    one step from an arbitrary stored state against the oracle's FP64 step
+    from the decoded state, within the storage rounding."""
+    rng = np.random.default_rng(9500 + seed)
+    while True:
+        nx, ny, nz = (int(v) for v in rng.integers(1, 41, size=3))
+        if nx * ny * nz <= 24000:
+            break
+    bc = [int(v) for v in rng.choice([D, A, P], size=6)]
+    for d in range(3):
+        if P in (bc[2 * d], bc[2 * d + 1]):
+            bc[2 * d] = bc[2 * d + 1] = P
+    prec = (W.FP32, W.FP16S, W.BF16S)[seed % 3]
+    flow = int(rng.integers(0, 2))
+    model = W.MRT if rng.uniform() < 0.5 else W.SRT
+    t_shift = 0.3 if prec != W.FP32 else 0.0
+    cfg = W.base_config(nx, ny, nz, flow=flow, enth_model=model, precision=prec, face_bc=bc,
+                        face_T=[float(v) for v in rng.uniform(-0.5, 1.0, size=6)], g_beta=4e-3,
+                        latent=1.5, lambda_s=0.09, lambda_l=0.12, cp_l=1.3, nu=0.04,
+                        T_shift=t_shift)
+    launch = (int(rng.choice([64, 128, 192, 256])), int(rng.choice([0, 8, 24])),
+              int(rng.integers(0, 17)), int(rng.choice([0, 1, 3, 16, 1 << 20])))
+    f, g = W.random_populations(cfg, seed=9600 + seed, f_scale=W19)
+    walls = random_walls(cfg, seed=9700 + seed)
+    tw = W.wall_fields(cfg, walls)
+    cav = make_cavity(cfg, walls=walls)
+    cav.set_launch(*launch)
+    cav.set_state(f, g)
+    f0, g0 = cav.state()
+    st = (f0.cpu().numpy() if flow else None, g0.cpu().numpy())
+    cav.step(1)
+    f1, g1 = cav.state()
+    ref = oracle.run(dict(cfg, precision=W.FP64), st, 1, tw=tw)
+    worst = _storage_step_error(cfg, prec, flow, t_shift, f1, g1, ref)
+    print(f"seed {seed}: {nx}x{ny}x{nz} {['fp64', 'fp32', 'fp16s', 'bf16s'][prec]} faces {bc} "
+          f"flow {flow} launch {launch}: largest error / bound {worst:.3f}")
+    assert worst < 1.0
