@@ -25,6 +25,20 @@ def rel(a, b):
     return float(np.abs(a - b).max() / (scale if scale > 0 else 1.0))
 
 
+def rel_from(a, b, b0, frac=1e-2):
+    """rel() for runs that relax toward rest: each population plane of a
+    against b, with the plane's scale floored at frac times its largest value
+    in the starting state b0 (the moving populations of a box that settles to
+    a uniform state shrink by orders of magnitude while rounding differences
+    keep the size set by the larger quantities of the collision)."""
+    a, b, b0 = _np(a), _np(b), _np(b0)
+    out = 0.0
+    for q in range(b.shape[0]):
+        scale = max(np.abs(b[q]).max(), frac * np.abs(b0[q]).max())
+        out = max(out, float(np.abs(a[q] - b[q]).max() / (scale if scale > 0 else 1.0)))
+    return out
+
+
 def plane_scales(b):
     """Largest |value| of every population plane (diagnostics)."""
     b = _np(b)

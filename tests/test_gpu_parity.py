@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import W19, absdiff, make_cavity, random_walls, rel
+from gpu_util import W19, absdiff, make_cavity, random_walls, rel, rel_from
 
 pytestmark = pytest.mark.gpu
 
@@ -208,6 +208,61 @@ def test_batch_of_uneven_cavities_matches_separate_oracle_runs():
         assert b[i, 1] == pytest.approx(rf["rho"].sum(), rel=1e-13), i
         assert b[i, 2] == pytest.approx(rf["fl"].sum(), rel=1e-12, abs=1e-12), i
         assert b[i, 3] == pytest.approx(hist[:, 3].sum(), rel=1e-11, abs=1e-9), i
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches_match_separate_oracle_runs(seed):
+    """Seeded batches of 2 to 5 cavities (dimensions 1 to 24, their own face
+    types, latent heat, conductivities, viscosity, buoyancy and wall
+    temperatures, random initial temperatures) in one launch with a random
+    launch shape, 40 steps: every cavity's state equals its own oracle run to
+    1e-12 of each population plane (floored at a tenth of the plane's
+    starting scale: a small periodic box settles toward a uniform state, and
+    its moving populations shrink a hundredfold in 40 steps while rounding
+    keeps the size set by h and T), and its H and mass budgets match."""
+    rng = np.random.default_rng(7700 + seed)
+    flow = int(rng.integers(0, 2))
+    model = W.MRT if rng.uniform() < 0.5 else W.SRT
+    cfgs = []
+    for _ in range(int(rng.integers(2, 6))):
+        while True:
+            nx, ny, nz = (int(v) for v in rng.integers(1, 25, size=3))
+            if nx * ny * nz <= 6000:
+                break
+        bc = [int(v) for v in rng.choice([W.DIRICHLET, W.ADIABATIC, W.PERIODIC], size=6)]
+        for d in range(3):
+            if W.PERIODIC in (bc[2 * d], bc[2 * d + 1]):
+                bc[2 * d] = bc[2 * d + 1] = W.PERIODIC
+        lam = float(rng.uniform(0.05, 0.15))
+        cfgs.append(W.base_config(
+            nx, ny, nz, flow=flow, enth_model=model, precision=W.FP64, face_bc=bc,
+            face_T=[float(v) for v in rng.uniform(-0.5, 1.2, size=6)],
+            latent=float(rng.uniform(0.5, 3.0)), lambda_s=lam,
+            lambda_l=lam * float(rng.uniform(0.7, 1.4)), cp_l=float(rng.uniform(1.0, 1.5)),
+            nu=float(rng.uniform(0.02, 0.1)), g_beta=float(rng.uniform(0.0, 5e-3))))
+    T0s = [W.random_temperature(c, seed=7800 + 10 * seed + i, lo=-0.3, hi=1.1)
+           for i, c in enumerate(cfgs)]
+    launch = (int(rng.choice([64, 128, 192, 256])), int(rng.choice([0, 8, 24])),
+              int(rng.integers(0, 17)), int(rng.choice([0, 1, 3, 16, 1 << 20])))
+    from paper_1703_02652_amd import Cavity
+    cav = Cavity(cfgs, T0=T0s, device="cuda")
+    cav.set_launch(*launch)
+    cav.step(40)
+    b = cav.budgets()
+    worst = 0.0
+    for i, c in enumerate(cfgs):
+        f, g = cav.state(i)
+        st0 = oracle.init_state(c, T0s[i])
+        ref = oracle.run(c, st0, 40)
+        e = max(rel_from(g, ref[1], st0[1], 0.1), rel_from(f, ref[0], st0[0], 0.1) if flow else 0.0)
+        worst = max(worst, e)
+        assert e < FP64_TOL, i
+        rf = oracle.fields(c, ref)
+        assert b[i, 0] == pytest.approx(rf["h"].sum(), rel=1e-12, abs=1e-12), i
+        if flow:
+            assert b[i, 1] == pytest.approx(rf["rho"].sum(), rel=1e-13), i
+    print(f"seed {seed}: {len(cfgs)} cavities {[(c['nx'], c['ny'], c['nz']) for c in cfgs]} "
+          f"flow {flow} launch {launch}: {worst:.1e}")
 
 
 def test_budgets_fp64_conservation_and_wall_flux():
