@@ -76,6 +76,62 @@ def test_adjoint_wall_gradient_matches_oracle_tangent(kind):
     assert np.all(dtw[nonfixed] == 0)
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_random_adjoint_cases_match_oracle_tangent(seed):
+    """Seeded sweep of the adjoint: lattice dimensions 3 to 10, random face
+    types with at least the x- face at a fixed temperature, flow on or off,
+    SRT or MRT, equal or different phase properties, a random checkpoint
+    interval (every step, short segments or one segment), run length, loss and
+    launch shape; dL/dT_w at up to 12 random wall nodes equals the oracle's
+    dual-number tangent to 1e-9 relative (FP64)."""
+    rng = np.random.default_rng(4400 + seed)
+    nx, ny, nz = (int(v) for v in rng.integers(3, 11, size=3))
+    bc = [int(v) for v in rng.choice([W.DIRICHLET, W.ADIABATIC, W.PERIODIC], size=6)]
+    for d in range(3):
+        if W.PERIODIC in (bc[2 * d], bc[2 * d + 1]):
+            bc[2 * d] = bc[2 * d + 1] = W.PERIODIC
+    bc[0] = W.DIRICHLET
+    if bc[1] == W.PERIODIC:
+        bc[1] = W.ADIABATIC
+    flow = int(rng.integers(0, 2))
+    model = W.MRT if rng.uniform() < 0.5 else W.SRT
+    kw = dict(flow=flow, enth_model=model, precision=W.FP64, face_bc=bc,
+              face_T=[float(v) for v in rng.uniform(-0.2, 1.0, size=6)], latent=1.2,
+              lambda_s=0.1, lambda_l=0.1, nu=0.05, g_beta=3e-3)
+    if rng.uniform() < 0.5:
+        kw.update(cp_l=1.4, lambda_l=0.06, T_m=0.1)
+    cfg = W.base_config(nx, ny, nz, **kw)
+    walls = {f: cfg["face_T"][f] + 0.05 * rng.uniform(-1, 1, size=shp)
+             for f, shp in enumerate(W.face_shapes(cfg)) if cfg["face_bc"][f] == W.DIRICHLET}
+    tw = W.wall_fields(cfg, walls)
+    T0 = W.random_temperature(cfg, seed=4500 + seed, lo=-0.2, hi=0.9, frac_at_melt=0.3)
+    nsteps = int(rng.integers(10, 31))
+    every = int(rng.choice([1, 3, 7, 50]))
+    loss = int(rng.integers(0, 2))
+    warm = int(rng.integers(5, 21))
+    launch = (int(rng.choice([64, 128, 192, 256])), 0, int(rng.integers(0, 17)),
+              int(rng.choice([0, 1, 3])))
+    cav = make_cavity(cfg, T0=T0, walls=walls)
+    cav.set_launch(*launch)
+    cav.step(warm)
+    st = oracle.run(cfg, oracle.init_state(cfg, T0), warm, tw=tw)
+    L = cav.adjoint_forward(nsteps, every, loss=loss)
+    dtw, _ = cav.adjoint_backward()
+    dtw = dtw.cpu().numpy()
+    sizes = [int(np.prod(sh)) for sh in W.face_shapes(cfg)]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    pool = [i for f in walls for i in range(offs[f], offs[f + 1])]
+    nodes = sorted(int(v) for v in rng.choice(pool, size=min(12, len(pool)), replace=False))
+    Lref, dref = _tangents(cfg, st, nsteps, tw, nodes, loss_kind=loss)
+    assert L == pytest.approx(Lref, rel=1e-12)
+    scale = np.abs(dref).max()
+    err = np.abs(dtw[nodes] - dref).max() / scale
+    print(f"seed {seed}: {nx}x{ny}x{nz} faces {bc} flow {flow} model {model} every {every} "
+          f"steps {nsteps} loss {loss} launch {launch}: |dL/dTw| max {scale:.2e}, rel err {err:.1e}")
+    assert scale > 0.0
+    assert err < 1e-9
+
+
 def test_adjoint_initial_temperature_gradient_and_front_loss():
     """dL/dT0 (loss = front position) from the state made at creation, against the
     oracle tangent of initialisation + run along unit T0 directions."""
