@@ -365,3 +365,25 @@ def test_cavity128_y_mirror_commutes_with_the_step():
     a.close()
     b.close()
     torch.cuda.empty_cache()
+
+
+def test_every_field_mask_returns_the_planes_of_the_full_mask():
+    """lbpc_fields with each of the 31 masks writes exactly the planes of the
+    full mask that the mask names, in bit order (h, T, f_l, rho, u), bit for
+    bit."""
+    import itertools
+    cfg = W.melting_cavity(12, 1e5, 0.02, 0.1, precision=W.FP32)
+    cfg.update(ny=9, nz=7)
+    cav = make_cavity(cfg, T0=W.random_temperature(cfg, seed=21, lo=-0.2, hi=1.0))
+    cav.step(30)
+    names = ("h", "T", "fl", "rho", "u")
+    full = cav.fields(names=names)
+    full = {k: v.cpu().numpy() for k, v in full.items()}
+    for r in range(1, 6):
+        for sub in itertools.combinations(names, r):
+            got = cav.fields(names=sub)
+            want = [k for k in ("h", "T", "fl", "rho") if k in sub] + (
+                ["ux", "uy", "uz"] if "u" in sub else [])
+            assert sorted(got) == sorted(want), sub
+            for k in want:
+                assert np.array_equal(got[k].cpu().numpy(), full[k]), (sub, k)
